@@ -1,0 +1,121 @@
+"""Seeded synthetic (T) problems.
+
+This module only draws inputs; it computes no part of the triples correction.
+Both the CPU oracle (through the tests) and the device library consume what it
+returns, so it must stay free of either side's arithmetic.
+
+The recipe stands in for the converged CCSD amplitudes and Cholesky/DF
+factors of the paper's molecules, which are not available:
+
+* occupied orbital energies ~ U[-1.5, -0.3] Eh, virtual ones ~ U[0.1, 3.0] Eh
+  (left unsorted);
+* DF factors B^Q_pq ~ N(0, b_std^2), symmetric in the orbital pair: the
+  elements with p <= q are drawn i.i.d. and mirrored, so every element keeps
+  the same spread;
+* MP2-like doubles t_ij^ab = (ia|jb) / (e_i + e_j - e_a - e_b) with
+  (ia|jb) = sum_Q B^Q_ia B^Q_jb, so t_ij^ab = t_ji^ba holds exactly;
+* singles t_i^a ~ N(0, t1_std^2).
+
+Layouts are row-major FP64: eps_occ[o], eps_vir[v], t1[o][v], t2[o][o][v][v],
+B_oo[naux][o][o], B_ov[naux][o][v], B_vv[naux][v][v].
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Problem:
+    o: int
+    v: int
+    naux: int
+    eps_occ: np.ndarray
+    eps_vir: np.ndarray
+    t1: np.ndarray
+    t2: np.ndarray
+    B_oo: np.ndarray
+    B_ov: np.ndarray
+    B_vv: np.ndarray
+    seed: int = 0
+
+    @property
+    def n_triples(self) -> int:
+        o = self.o
+        return o * (o + 1) * (o + 2) // 6 - o
+
+
+# Shapes of the synthetic workloads: (o, v, naux, seed).
+SMALL = (6, 30, 90, 1)          # every triple checked against the oracle
+MEDIUM = (20, 200, 600, 2)      # single job, full (vv|vo) resident
+LARGE = (40, 400, 1200, 3)      # the throughput workload
+HUGE = (100, 800, 2400, 5)      # (vv|vo) assembled on the fly
+
+
+def _sym_normal(rng: np.random.Generator, naux: int, n: int, std: float) -> np.ndarray:
+    """naux symmetric n x n matrices; p<=q drawn i.i.d., mirrored below."""
+    out = np.empty((naux, n, n))
+    iu = np.triu_indices(n)
+    for q in range(naux):
+        m = np.zeros((n, n))
+        m[iu] = rng.standard_normal(len(iu[0])) * std
+        out[q] = m + np.triu(m, 1).T
+    return out
+
+
+def make_problem(o: int, v: int, naux: int, seed: int, *, b_std: float = 0.05,
+                 t1_std: float = 1e-3, with_t1: bool = True) -> Problem:
+    """Draw one synthetic closed-shell (T) problem."""
+    if o < 1 or v < 1 or naux < 1:
+        raise ValueError("o, v and naux must be positive")
+    rng = np.random.default_rng(seed)
+    eps_occ = rng.uniform(-1.5, -0.3, o)
+    eps_vir = rng.uniform(0.1, 3.0, v)
+    B_oo = _sym_normal(rng, naux, o, b_std)
+    B_ov = rng.standard_normal((naux, o, v)) * b_std
+    B_vv = _sym_normal(rng, naux, v, b_std)
+    t1 = rng.standard_normal((o, v)) * t1_std
+    if not with_t1:
+        t1[:] = 0.0
+    t2 = mp2_doubles(eps_occ, eps_vir, B_ov)
+    return Problem(o, v, naux, eps_occ, eps_vir, t1, t2, B_oo, B_ov, B_vv, seed)
+
+
+def mp2_doubles(eps_occ: np.ndarray, eps_vir: np.ndarray, B_ov: np.ndarray) -> np.ndarray:
+    """t2[i][j][a][b] = (ia|jb) / (e_i + e_j - e_a - e_b)."""
+    naux, o, v = B_ov.shape
+    L = B_ov.reshape(naux, o * v)
+    M = L.T @ L
+    M += M.T           # exact symmetry (ia|jb) = (jb|ia), whatever BLAS rounding did
+    M *= 0.5
+    t2 = np.ascontiguousarray(M.reshape(o, v, o, v).transpose(0, 2, 1, 3))
+    del M
+    # (e_i + e_j) - (e_a + e_b): both sums commute, so t_ij^ab = t_ji^ba bitwise
+    den = ((eps_occ[:, None, None, None] + eps_occ[None, :, None, None])
+           - (eps_vir[None, None, :, None] + eps_vir[None, None, None, :]))
+    t2 /= den
+    return t2
+
+
+def triple_list(o: int) -> np.ndarray:
+    """Occupied triples i<=j<=k, i=j=k left out, i-major; int32 [N_t][3]."""
+    out = [(i, j, k) for i in range(o) for j in range(i, o) for k in range(j, o)
+           if not (i == j == k)]
+    return np.asarray(out, dtype=np.int32).reshape(-1, 3)
+
+
+def sample_triples(o: int, n: int, seed: int) -> np.ndarray:
+    """A fixed seeded subset of n triples that always holds both
+    i=j<k and i<j=k kinds when they exist; returned in list order."""
+    allt = triple_list(o)
+    n = min(n, len(allt))
+    rng = np.random.default_rng(seed)
+    idx = set(rng.choice(len(allt), size=n, replace=False).tolist())
+    eq_ij = np.nonzero((allt[:, 0] == allt[:, 1]))[0]
+    eq_jk = np.nonzero((allt[:, 1] == allt[:, 2]))[0]
+    for pool in (eq_ij, eq_jk):
+        if len(pool) and not idx.intersection(pool.tolist()):
+            idx.pop()
+            idx.add(int(pool[rng.integers(len(pool))]))
+    return allt[sorted(idx)]
