@@ -1,0 +1,174 @@
+/*
+ * te.h -- C ABI of the MI355X (gfx950) perturbative-triples library.
+ *
+ * The library evaluates the (T) correction of closed-shell CCSD(T) as given
+ * in Fajen, Kelly, Hohenstein, Martinez, "Accelerating CCSD(T) on GPUs"
+ * (arXiv 2512.01055), section "Implementation Details":
+ *
+ *   E(T) = sum_{i<=j<=k} (2 - d_ij - d_jk) sum_{abc} (W + V)^{abc}_{ijk} Z^{abc}_{ijk} / D^{abc}_{ijk}
+ *
+ * with W from Eq. 2 summed over the six pair permutations of Eq. 5, the
+ * singles term V of Eq. 3, and D = e_i + e_j + e_k - e_a - e_b - e_c (Eq. 4
+ * with the sign of the paper's energy-kernel figure). Integrals are
+ * chemists' (pq|rs); the restricted sum over occupied triples is the same
+ * number as Eq. 1's restricted sum over virtual triples.
+ *
+ * All functions are extern "C", never throw, and report through te_status.
+ * A failing call leaves its output arguments untouched; te_last_error()
+ * returns a message for the calling thread's most recent failure.
+ */
+#ifndef TE_H
+#define TE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum te_status {
+  TE_OK = 0,
+  TE_PENDING = 1,     /* te_poll only: the job has not finished            */
+  TE_EINVAL = -1,     /* bad argument (sizes, NULL pointers, bad values)   */
+  TE_ENOMEM = -2,     /* the job cannot fit in the HBM budget              */
+  TE_EDEVICE = -3,    /* a HIP runtime call failed                         */
+  TE_EBUSY = -4,      /* the server is shutting down / queue full          */
+  TE_ENOTFOUND = -5,  /* unknown or already-collected ticket               */
+  TE_ECANCELED = -6   /* the server was destroyed before the job ran       */
+} te_status;
+
+/* Arithmetic of the W contractions (Eqs. 2 and 5). In every mode the
+ * denominators, the singles term, each triple's partial sum and E(T) itself
+ * are evaluated in FP64. */
+typedef enum te_precision {
+  TE_FP64 = 0,    /* FP64 MFMA                                                 */
+  TE_FP32 = 1,    /* operands rounded to FP32, FP32 MFMA, FP32 accumulation    */
+  TE_BF16X3 = 2,  /* operands split into 3 BF16 parts, 6 cross products,
+                     FP32 accumulation                                         */
+  TE_BF16X2 = 3   /* 2 BF16 parts, 3 cross products, FP32 accumulation         */
+} te_precision;
+
+typedef enum te_memkind { TE_MEM_HOST = 0, TE_MEM_DEVICE = 1 } te_memkind;
+
+/* One closed-shell (T) problem, canonical orbitals. Every array is row-major
+ * FP64 and every pointer lives in the memory named by `mem`.
+ *
+ *   eps_occ [o]            occupied orbital energies
+ *   eps_vir [v]            virtual orbital energies
+ *   t1      [o][v]         t1[i][a]       = t_i^a
+ *   t2      [o][o][v][v]   t2[i][j][a][b] = t_ij^ab, equal to t2[j][i][b][a]
+ *
+ * Integrals, either as density-fitting / Cholesky factors (Eq. 6; naux > 0)
+ *   B_oo [naux][o][o], B_ov [naux][o][v], B_vv [naux][v][v],
+ *   (pq|rs) = sum_Q B^Q_pq B^Q_rs, B_oo and B_vv symmetric in their pair,
+ * or, when naux == 0, explicitly
+ *   ovvv [o][v][v][v] = (ia|bc),  ovoo [o][v][o][o] = (ia|jk),
+ *   ovov [o][v][o][v] = (ia|jb).
+ * Pointers of the unused form may be NULL.
+ */
+typedef struct te_problem {
+  int32_t o, v, naux;
+  te_memkind mem;
+  const double *eps_occ, *eps_vir;
+  const double *t1, *t2;
+  const double *B_oo, *B_ov, *B_vv;
+  const double *ovvv, *ovoo, *ovov;
+} te_problem;
+
+/* How (vv|vo) slices are held. */
+typedef enum te_xmode {
+  TE_X_AUTO = 0,        /* materialise all o*v^3 when it fits, else on the fly */
+  TE_X_RESIDENT = 1,    /* materialise all slices at te_init                   */
+  TE_X_ON_THE_FLY = 2   /* assemble slices from B_ov, B_vv into a slice cache  */
+} te_xmode;
+
+typedef struct te_config {
+  int device;           /* HIP device ordinal                                     */
+  void *stream;         /* hipStream_t the work is ordered on; NULL: library-own  */
+  size_t hbm_budget;    /* bytes the job may allocate; 0: 90% of free memory      */
+  int validate;         /* 1: reject non-finite inputs and t2 asymmetry > 1e-12   */
+  te_xmode x_mode;
+  int x_cache_slices;   /* on-the-fly mode: slices kept resident; 0: automatic    */
+} te_config;
+
+typedef struct te_stats {
+  double seconds;        /* wall time of the call                                */
+  double flops;          /* algorithmic W flops: n_triples * 12 v^3 (v + o)      */
+  double tflops;         /* flops / seconds / 1e12                               */
+  int64_t n_triples;     /* occupied triples evaluated                           */
+  double stage_seconds;  /* part of `seconds` spent preparing operands           */
+  double assemble_flops; /* on-the-fly mode: flops spent assembling slices       */
+} te_stats;
+
+typedef struct te_job_s *te_job;
+
+/* Stage a problem on the device (integral assembly from the factors, padded
+ * device layouts). Host arrays are copied before the call returns; device
+ * arrays are read during the call and may be freed afterwards, except t2,
+ * which is borrowed (kept in use until te_free) when it is in device memory
+ * and v is a multiple of 8.
+ * Errors: TE_EINVAL for o < 1, v < 1, naux < 0, NULL required pointers or
+ * (validate) bad values; TE_ENOMEM when the staged footprint exceeds the
+ * budget; TE_EDEVICE for HIP failures. */
+te_status te_init(const te_problem *prob, const te_config *cfg, te_job *out);
+
+/* Evaluate E(T) over all occupied triples i<=j<=k (i=j=k contribute zero and
+ * are skipped). Blocks until done. `per_triple` (host, optional) receives
+ * the weighted partial of each triple in the order of te_triple_list.
+ * The result is bitwise reproducible for a given problem and precision. */
+te_status te_energy(te_job job, te_precision prec, double *e_t, double *per_triple,
+                    te_stats *st);
+
+/* Evaluate only the listed triples: ijk is a host array [n][3] of
+ * 0 <= i <= j <= k < o (not all equal). e_sum (optional) receives their
+ * sum, per_triple (optional, host [n]) each weighted partial. */
+te_status te_energy_triples(te_job job, te_precision prec, const int32_t *ijk, int64_t n,
+                            double *e_sum, double *per_triple, te_stats *st);
+
+te_status te_free(te_job job);
+
+/* Number of triples i<=j<=k, not all equal: o(o+1)(o+2)/6 - o. */
+int64_t te_num_triples(int32_t o);
+/* Writes the triple list (i-major) into ijk [te_num_triples(o)][3]. */
+te_status te_triple_list(int32_t o, int32_t *ijk);
+/* Algorithmic flop count of one triple's W: 12 v^3 (v + o). */
+double te_flops_per_triple(int32_t o, int32_t v);
+
+/* ---------------------------------------------------------------------
+ * Serving: jobs of mixed (o, v) arrive while others run. The server admits
+ * each job once its HBM footprint fits the budget, stages it, and packs its
+ * triple work with that of the other resident jobs into shared launches.
+ * A job's result is bitwise the same as te_energy would give alone.
+ * te_submit / te_poll / te_wait may be called from any thread.
+ * ------------------------------------------------------------------- */
+typedef struct te_server_s *te_server;
+
+typedef struct te_server_config {
+  int device;
+  size_t hbm_budget;      /* bytes for resident jobs; 0: 80% of free memory */
+  int max_resident_jobs;  /* 0: 64                                           */
+  int max_queued_jobs;    /* 0: 4096                                         */
+} te_server_config;
+
+te_status te_server_create(const te_server_config *cfg, te_server *out);
+/* Copies the problem (host memory only) and queues it. Returns TE_ENOMEM if
+ * the job could never fit the budget, TE_EBUSY if the queue is full. */
+te_status te_submit(te_server srv, const te_problem *prob, te_precision prec,
+                    uint64_t *ticket);
+/* TE_PENDING while queued or running; the job's final status otherwise
+ * (TE_OK with e_t and st filled in). The ticket is released by the first
+ * final answer; later polls return TE_ENOTFOUND. */
+te_status te_poll(te_server srv, uint64_t ticket, double *e_t, te_stats *st);
+/* te_poll that blocks until the job is final. */
+te_status te_wait(te_server srv, uint64_t ticket, double *e_t, te_stats *st);
+/* Stops the server; jobs not yet finished end with TE_ECANCELED. */
+te_status te_server_destroy(te_server srv);
+
+const char *te_strerror(te_status s);
+const char *te_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TE_H */

@@ -1,0 +1,578 @@
+// C-ABI host side of the (T) library: validation, staging of the padded
+// device layouts, precision copies, triple scheduling and launch ordering.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "te.h"
+#include "te_internal.h"
+#include "te_job.h"
+
+namespace te {
+
+thread_local std::string g_last_error;
+
+Fail::Fail(te_status s_, std::string m) : s(s_), msg(std::move(m)) {}
+
+void hip_check(hipError_t e, const char *what, int line) {
+  if (e != hipSuccess)
+    throw Fail(TE_EDEVICE, std::string(what) + " (line " + std::to_string(line) +
+                               "): " + hipGetErrorString(e));
+}
+
+te_status set_error(te_status s, const std::string &m) {
+  g_last_error = m;
+  return s;
+}
+
+// ------------------------------------------------------------ DBuf
+DBuf::~DBuf() { release(); }
+void DBuf::release() {
+  if (p) (void)hipFree(p);
+  if (acct) *acct -= bytes;
+  p = nullptr;
+  bytes = 0;
+  acct = nullptr;
+}
+void DBuf::alloc(size_t n, size_t *account, size_t budget) {
+  release();
+  if (n == 0) n = 16;
+  if (account && *account + n > budget)
+    throw Fail(TE_ENOMEM, "device allocation of " + std::to_string(n) +
+                              " bytes exceeds the HBM budget (" + std::to_string(*account) +
+                              " of " + std::to_string(budget) + " in use)");
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    p = nullptr;
+    throw Fail(TE_ENOMEM, "hipMalloc(" + std::to_string(n) + "): " + hipGetErrorString(e));
+  }
+  bytes = n;
+  acct = account;
+  if (acct) *acct += n;
+}
+
+// ------------------------------------------------------------ triples
+std::vector<int> triple_list_host(int o) {
+  std::vector<int> t;
+  for (int i = 0; i < o; ++i)
+    for (int j = i; j < o; ++j)
+      for (int k = j; k < o; ++k)
+        if (!(i == j && j == k)) { t.push_back(i); t.push_back(j); t.push_back(k); }
+  return t;
+}
+
+std::vector<int> sextet_list(int nT) {
+  std::vector<int> s;
+  s.reserve((size_t)nT * (nT + 1) * (nT + 2) / 6);
+  for (int A = 0; A < nT; ++A)
+    for (int B = 0; B <= A; ++B)
+      for (int C = 0; C <= B; ++C) s.push_back(A | (B << 10) | (C << 20));
+  return s;
+}
+
+static size_t elem_size(Prec p) {
+  return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2);
+}
+static int nparts(Prec p) { return p == Prec::BF16X3 || p == Prec::BF16X2 ? 3 : 1; }
+static size_t out_size(Prec p) { return p == Prec::F64 ? 8 : 4; }
+
+// ------------------------------------------------------------ staging
+static void copy_in(Job &J, const double *src, size_t n, DBuf &dst, bool device_src) {
+  dst.alloc(n * sizeof(double), &J.used, J.budget);
+  HIPCHK(hipMemcpyAsync(dst.p, src, n * sizeof(double),
+                        device_src ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, J.s_main));
+}
+
+// Make a device-resident unpadded copy (or borrow a device pointer).
+static const double *device_view(Job &J, const double *src, size_t n, DBuf &tmp) {
+  if (J.mem == TE_MEM_DEVICE) return src;
+  copy_in(J, src, n, tmp, false);
+  return tmp.as<double>();
+}
+
+static void stage_padded(Job &J, const double *src, int d0, int d1, int d2, int d3, int p1,
+                         int p2, int p3, double scale, DBuf &dst) {
+  size_t n = (size_t)d0 * p1 * p2 * p3;
+  dst.alloc(n * sizeof(double), &J.used, J.budget);
+  HIPCHK(hipMemsetAsync(dst.p, 0, n * sizeof(double), J.s_main));
+  DBuf tmp;
+  const double *s = device_view(J, src, (size_t)d0 * d1 * d2 * d3, tmp);
+  HIPCHK(launch_pad4(s, dst.as<double>(), d0, d1, d2, d3, p1, p2, p3, scale, J.s_main));
+  if (tmp.p) HIPCHK(hipStreamSynchronize(J.s_main));
+}
+
+static void gemm_stage(Job &J, const double *A, long lda, const double *B, long ldb, int M,
+                       int N, int K, int rd, long rs1, long rs2, int cd, long cs1, long cs2,
+                       double alpha, double *C) {
+  GemmTN g{A, B, C, M, N, K, lda, ldb, rd, rs1, rs2, cd, cs1, cs2, alpha};
+  HIPCHK(launch_gemm_tn(g, J.s_main));
+}
+
+void stage_df_slices(Job &J, const int *occ, int n, double *dst, size_t slice_stride) {
+  // X_p[x][y][f] = (px|yf) = sum_Q B^Q_px B^Q_yf   (Eq. 6)
+  const int o = J.o, v = J.v, vp = J.vp, naux = J.naux;
+  const long vp2 = (long)vp * vp;
+  for (int q = 0; q < n; ++q) {
+    double *C = dst + (size_t)q * slice_stride;
+    HIPCHK(hipMemsetAsync(C, 0, (size_t)vp2 * vp * sizeof(double), J.s_main));
+    gemm_stage(J, J.Bov + (long)occ[q] * v, (long)o * v, J.Bvv, (long)v * v, v, v * v, naux,
+               v, vp2, vp2, v, vp, 1, 1.0, C);
+  }
+}
+
+static void stage(Job &J, const te_problem &P) {
+  const int o = J.o, v = J.v, vp = J.vp;
+  const bool dev = P.mem == TE_MEM_DEVICE;
+  hipStream_t s = J.s_main;
+
+  // orbital energies and singles, padded in v
+  copy_in(J, P.eps_occ, o, J.eo, dev);
+  {
+    DBuf tmp;
+    const double *ev = device_view(J, P.eps_vir, v, tmp);
+    J.ev.alloc((size_t)vp * 8, &J.used, J.budget);
+    HIPCHK(hipMemsetAsync(J.ev.p, 0, (size_t)vp * 8, s));
+    HIPCHK(hipMemcpyAsync(J.ev.p, ev, (size_t)v * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  stage_padded(J, P.t1, 1, 1, o, v, 1, o, vp, 1.0, J.t1);
+
+  // doubles: borrowed when already in device memory with an aligned v
+  if (dev && vp == v) {
+    J.t2 = P.t2;
+  } else {
+    stage_padded(J, P.t2, o, o, v, v, o, vp, vp, 1.0, J.t2_own);
+    J.t2 = J.t2_own.as<double>();
+  }
+
+  const size_t nX = (size_t)o * vp * vp * vp;
+  if (J.naux > 0) {
+    const int naux = J.naux;
+    J.Bov = device_view(J, P.B_ov, (size_t)naux * o * v, J.Bov_own);
+    J.Boo = device_view(J, P.B_oo, (size_t)naux * o * o, J.Boo_own);
+    J.Bvv = device_view(J, P.B_vv, (size_t)naux * v * v, J.Bvv_own);
+    // K[p][x][q][y] = (px|qy), for V (Eq. 3)
+    J.K.alloc((size_t)o * vp * o * vp * 8, &J.used, J.budget);
+    HIPCHK(hipMemsetAsync(J.K.p, 0, J.K.bytes, s));
+    gemm_stage(J, J.Bov, (long)o * v, J.Bov, (long)o * v, o * v, o * v, naux, v,
+               (long)vp * o * vp, (long)o * vp, v, vp, 1, 1.0, J.K.as<double>());
+    // In[p][x][q][l] = -(px|ql), the occupied term of Eq. 2 with its sign
+    J.In.alloc((size_t)o * vp * o * o * 8, &J.used, J.budget);
+    HIPCHK(hipMemsetAsync(J.In.p, 0, J.In.bytes, s));
+    gemm_stage(J, J.Bov, (long)o * v, J.Boo, (long)o * o, o * v, o * o, naux, v,
+               (long)vp * o * o, (long)o * o, o * o, 0, 1, -1.0, J.In.as<double>());
+    if (J.x_resident) {
+      J.X.alloc(nX * 8, &J.used, J.budget);
+      std::vector<int> all(o);
+      for (int p = 0; p < o; ++p) all[p] = p;
+      stage_df_slices(J, all.data(), o, J.X.as<double>(), (size_t)vp * vp * vp);
+      HIPCHK(hipStreamSynchronize(s));
+      // factors are no longer needed once every slice is resident
+      J.Bov_own.release(); J.Boo_own.release(); J.Bvv_own.release();
+      J.Bov = J.Boo = J.Bvv = nullptr;
+    }
+  } else {
+    stage_padded(J, P.ovov, o, v, o, v, vp, o, vp, 1.0, J.K);
+    stage_padded(J, P.ovoo, o, v, o, o, vp, o, o, -1.0, J.In);
+    stage_padded(J, P.ovvv, o, v, v, v, vp, vp, vp, 1.0, J.X);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+static void validate_device(Job &J, const te_problem &P) {
+  // non-finite values anywhere in the staged data, and t2 pair symmetry
+  DBuf flag;
+  flag.alloc(64, nullptr, 0);
+  HIPCHK(hipMemsetAsync(flag.p, 0, 64, J.s_main));
+  auto chk = [&](const void *p, size_t n) {
+    if (p && n) HIPCHK(launch_check((const double *)p, n, flag.as<int>(), J.s_main));
+  };
+  chk(J.eo.p, J.eo.bytes / 8);
+  chk(J.ev.p, J.ev.bytes / 8);
+  chk(J.t1.p, J.t1.bytes / 8);
+  chk(J.t2, (size_t)J.o * J.o * J.vp * J.vp);
+  chk(J.K.p, J.K.bytes / 8);
+  chk(J.In.p, J.In.bytes / 8);
+  chk(J.X.p, J.X.bytes / 8);
+  HIPCHK(launch_t2_asym(J.t2, J.o, J.vp, (double *)(flag.as<char>() + 16), nullptr, J.s_main));
+  int bad = 0;
+  double mm[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(&bad, flag.p, 4, hipMemcpyDeviceToHost, J.s_main));
+  HIPCHK(hipMemcpyAsync(mm, flag.as<char>() + 16, 16, hipMemcpyDeviceToHost, J.s_main));
+  HIPCHK(hipStreamSynchronize(J.s_main));
+  (void)P;
+  if (bad) throw Fail(TE_EINVAL, "input holds a non-finite value");
+  if (mm[0] > 1e-12 * std::max(mm[1], 1e-300))
+    throw Fail(TE_EINVAL, "t2 is not pair-symmetric: max |t_ij^ab - t_ji^ba| = " +
+                              std::to_string(mm[0]));
+}
+
+// ------------------------------------------------------------ precisions
+const Operands &ensure_prec(Job &J, Prec p) {
+  int slot = (p == Prec::BF16X2) ? (int)Prec::BF16X3 : (int)p;
+  Operands &op = J.op[slot];
+  if (op.ready) return op;
+  const int o = J.o, vp = J.vp;
+  const size_t nT2 = (size_t)o * o * vp * vp;
+  const size_t nIn = (size_t)o * vp * o * o;
+  const size_t nX = J.X.p ? (size_t)o * vp * vp * vp : 0;
+  if (p == Prec::F64) {
+    op.X = J.X.p; op.T2 = J.t2; op.In = J.In.p;
+    op.xps = nX; op.tps = nT2; op.ips = nIn;
+  } else if (p == Prec::F32) {
+    op.T2_own.alloc(nT2 * 4, &J.used, J.budget);
+    op.In_own.alloc(nIn * 4, &J.used, J.budget);
+    HIPCHK(launch_to_f32(J.t2, op.T2_own.as<float>(), nT2, J.s_main));
+    HIPCHK(launch_to_f32(J.In.as<double>(), op.In_own.as<float>(), nIn, J.s_main));
+    if (nX) {
+      op.X_own.alloc(nX * 4, &J.used, J.budget);
+      HIPCHK(launch_to_f32(J.X.as<double>(), op.X_own.as<float>(), nX, J.s_main));
+    }
+    op.X = op.X_own.p; op.T2 = op.T2_own.p; op.In = op.In_own.p;
+    op.xps = nX; op.tps = nT2; op.ips = nIn;
+  } else {
+    op.T2_own.alloc(nT2 * 2 * 3, &J.used, J.budget);
+    op.In_own.alloc(nIn * 2 * 3, &J.used, J.budget);
+    HIPCHK(launch_to_bf16_parts(J.t2, op.T2_own.as<uint16_t>(), nT2, 3, J.s_main));
+    HIPCHK(launch_to_bf16_parts(J.In.as<double>(), op.In_own.as<uint16_t>(), nIn, 3, J.s_main));
+    if (nX) {
+      op.X_own.alloc(nX * 2 * 3, &J.used, J.budget);
+      HIPCHK(launch_to_bf16_parts(J.X.as<double>(), op.X_own.as<uint16_t>(), nX, 3, J.s_main));
+    }
+    op.X = op.X_own.p; op.T2 = op.T2_own.p; op.In = op.In_own.p;
+    op.xps = nX; op.tps = nT2; op.ips = nIn;
+  }
+  HIPCHK(hipStreamSynchronize(J.s_main));
+  op.ready = true;
+  return op;
+}
+
+// ------------------------------------------------------------ execution
+double flops_per_triple(int o, int v) { return 12.0 * (double)v * v * v * ((double)v + o); }
+
+static int batch_size(const Job &J, Prec p, long ntr) {
+  const int bm = wbuild_bm();
+  const int nb = wbuild_pick_nb(J.vp);
+  const long mt = ((long)J.vp * J.vp + bm - 1) / bm;
+  const long nt = (J.vp + 16 * nb - 1) / (16 * nb);
+  const long tiles = 3 * mt * nt;
+  long b = std::max(1L, (16384 + tiles - 1) / tiles);
+  // W scratch for two batches in flight
+  const size_t per = 3 * (size_t)J.vp * J.vp * J.vp * out_size(p);
+  const size_t cap = std::max<size_t>(per, (size_t)4 << 30);
+  b = std::min<long>(b, std::max<long>(1, (long)(cap / per)));
+  b = std::min<long>(b, ntr);
+  return (int)std::max(1L, b);
+}
+
+void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double *per_triple,
+                 te_stats *st) {
+  auto t0 = std::chrono::steady_clock::now();
+  const Operands &op = ensure_prec(J, p);
+  auto t1 = std::chrono::steady_clock::now();
+  if (!J.X.p) throw Fail(TE_EINVAL, "(vv|vo) slices are not resident");
+
+  const int o = J.o, vp = J.vp;
+  const int bm = wbuild_bm();
+  const int nbk = wbuild_pick_nb(vp);
+  const int mt = (int)(((long)vp * vp + bm - 1) / bm);
+  const int nt = (vp + 16 * nbk - 1) / (16 * nbk);
+  const int tiles = 3 * mt * nt;
+  const int B = batch_size(J, p, ntr);
+  const size_t vp3 = (size_t)vp * vp * vp;
+  const size_t osz = out_size(p);
+  const long nbatch = (ntr + B - 1) / B;
+
+  // scratch: W for two batches, partials for two batches, per-triple results
+  DBuf wbuf, part, eout, esum, witems, eitems, ritems;
+  wbuf.alloc(2 * (size_t)B * 3 * vp3 * osz, &J.used, J.budget);
+  part.alloc(2 * (size_t)B * J.nsext * 8, &J.used, J.budget);
+  eout.alloc((size_t)ntr * 8, &J.used, J.budget);
+  esum.alloc(8, &J.used, J.budget);
+
+  std::vector<WItem> wi(ntr);
+  std::vector<EItem> ei(ntr);
+  std::vector<RItem> ri(ntr);
+  const size_t xs = vp3;  // slice stride in the resident layout
+  for (long t = 0; t < ntr; ++t) {
+    const int i = ijk[3 * t], j = ijk[3 * t + 1], k = ijk[3 * t + 2];
+    const long b = t / B, slot = b & 1, q = t - b * B;
+    void *W = wbuf.as<char>() + ((size_t)slot * B + q) * 3 * vp3 * osz;
+    const size_t es = elem_size(p);
+    WItem &w = wi[t];
+    w.Xs[0] = (const char *)op.X + (size_t)i * xs * es;
+    w.Xs[1] = (const char *)op.X + (size_t)j * xs * es;
+    w.Xs[2] = (const char *)op.X + (size_t)k * xs * es;
+    w.T2 = op.T2; w.In = op.In;
+    w.xps = op.xps; w.tps = op.tps; w.ips = op.ips;
+    w.W = W; w.o = o; w.vp = vp; w.i = i; w.j = j; w.k = k; w.mt = mt; w.nt = nt;
+    EItem &e = ei[t];
+    e.W = W; e.K = J.K.as<double>(); e.t1 = J.t1.as<double>();
+    e.eo = J.eo.as<double>(); e.ev = J.ev.as<double>(); e.sext = J.sext.as<int>();
+    e.part = part.as<double>() + ((size_t)slot * B + q) * J.nsext;
+    e.o = o; e.v = J.v; e.vp = vp; e.nT = vp / BOX; e.i = i; e.j = j; e.k = k;
+    e.nsext = J.nsext;
+    RItem &r = ri[t];
+    r.part = e.part; r.out = eout.as<double>() + t; r.n = J.nsext;
+    r.w = 2.0 - (i == j) - (j == k);
+  }
+  witems.alloc(ntr * sizeof(WItem), &J.used, J.budget);
+  eitems.alloc(ntr * sizeof(EItem), &J.used, J.budget);
+  ritems.alloc(ntr * sizeof(RItem), &J.used, J.budget);
+  HIPCHK(hipMemcpyAsync(witems.p, wi.data(), ntr * sizeof(WItem), hipMemcpyHostToDevice, J.s_main));
+  HIPCHK(hipMemcpyAsync(eitems.p, ei.data(), ntr * sizeof(EItem), hipMemcpyHostToDevice, J.s_main));
+  HIPCHK(hipMemcpyAsync(ritems.p, ri.data(), ntr * sizeof(RItem), hipMemcpyHostToDevice, J.s_main));
+  HIPCHK(hipEventRecord(J.ev_start, J.s_main));
+  HIPCHK(hipStreamWaitEvent(J.s_aux, J.ev_start, 0));
+
+  const bool f64 = p == Prec::F64;
+  for (long b = 0; b < nbatch; ++b) {
+    const int slot = (int)(b & 1);
+    const long first = b * B;
+    const int cnt = (int)std::min<long>(B, ntr - first);
+    if (b >= 2) HIPCHK(hipStreamWaitEvent(J.s_aux, J.ev_e[slot], 0));
+    HIPCHK(launch_wbuild(p, witems.as<WItem>() + first, nullptr, cnt, tiles, (long)cnt * tiles,
+                         nbk, J.s_aux));
+    HIPCHK(hipEventRecord(J.ev_w[slot], J.s_aux));
+    HIPCHK(hipStreamWaitEvent(J.s_main, J.ev_w[slot], 0));
+    HIPCHK(launch_energy(f64, eitems.as<EItem>() + first, nullptr, cnt, J.nsext,
+                         (long)cnt * J.nsext, J.s_main));
+    HIPCHK(launch_reduce(ritems.as<RItem>() + first, cnt, J.s_main));
+    HIPCHK(hipEventRecord(J.ev_e[slot], J.s_main));
+  }
+  HIPCHK(launch_sum(eout.as<double>(), ntr, esum.as<double>(), J.s_main));
+  double E = 0.0;
+  HIPCHK(hipMemcpyAsync(&E, esum.p, 8, hipMemcpyDeviceToHost, J.s_main));
+  if (per_triple)
+    HIPCHK(hipMemcpyAsync(per_triple, eout.p, ntr * 8, hipMemcpyDeviceToHost, J.s_main));
+  HIPCHK(hipStreamSynchronize(J.s_main));
+  auto t2 = std::chrono::steady_clock::now();
+  if (e_sum) *e_sum = E;
+  if (st) {
+    st->seconds = std::chrono::duration<double>(t2 - t0).count();
+    st->stage_seconds = std::chrono::duration<double>(t1 - t0).count();
+    st->n_triples = ntr;
+    st->flops = (double)ntr * flops_per_triple(o, J.v);
+    st->tflops = st->flops / std::max(st->seconds, 1e-12) / 1e12;
+    st->assemble_flops = 0.0;
+  }
+}
+
+Job::~Job() {
+  if (dev_set) (void)hipSetDevice(device);
+  if (s_main) (void)hipStreamSynchronize(s_main);
+  if (s_aux) {
+    (void)hipStreamSynchronize(s_aux);
+    (void)hipStreamDestroy(s_aux);
+  }
+  for (int q = 0; q < 2; ++q) {
+    if (ev_w[q]) (void)hipEventDestroy(ev_w[q]);
+    if (ev_e[q]) (void)hipEventDestroy(ev_e[q]);
+  }
+  if (ev_start) (void)hipEventDestroy(ev_start);
+  if (own_main && s_main) (void)hipStreamDestroy(s_main);
+}
+
+static void check_problem(const te_problem *P) {
+  if (!P) throw Fail(TE_EINVAL, "problem is NULL");
+  if (P->o < 1 || P->v < 1 || P->naux < 0)
+    throw Fail(TE_EINVAL, "need o >= 1, v >= 1, naux >= 0");
+  if (pad_v(P->v) / BOX > 1023) throw Fail(TE_EINVAL, "v above 8184 is not supported");
+  if (P->mem != TE_MEM_HOST && P->mem != TE_MEM_DEVICE) throw Fail(TE_EINVAL, "bad memory kind");
+  if (!P->eps_occ || !P->eps_vir || !P->t1 || !P->t2)
+    throw Fail(TE_EINVAL, "eps_occ, eps_vir, t1 and t2 are required");
+  if (P->naux > 0 && (!P->B_oo || !P->B_ov || !P->B_vv))
+    throw Fail(TE_EINVAL, "naux > 0 needs B_oo, B_ov and B_vv");
+  if (P->naux == 0 && (!P->ovvv || !P->ovoo || !P->ovov))
+    throw Fail(TE_EINVAL, "naux == 0 needs ovvv, ovoo and ovov");
+}
+
+static void check_host_values(const te_problem &P) {
+  if (P.mem != TE_MEM_HOST) return;
+  auto finite = [](const double *x, size_t n) {
+    for (size_t q = 0; q < n; ++q)
+      if (!std::isfinite(x[q])) return false;
+    return true;
+  };
+  const size_t o = P.o, v = P.v;
+  if (!finite(P.eps_occ, o) || !finite(P.eps_vir, v) || !finite(P.t1, o * v))
+    throw Fail(TE_EINVAL, "input holds a non-finite value");
+}
+
+Job *make_job(const te_problem *P, const te_config *cfg_in) {
+  check_problem(P);
+  te_config cfg{};
+  if (cfg_in) cfg = *cfg_in;
+  if (cfg.x_mode < TE_X_AUTO || cfg.x_mode > TE_X_ON_THE_FLY)
+    throw Fail(TE_EINVAL, "bad x_mode");
+  if (cfg.validate) check_host_values(*P);
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (cfg.device < 0 || cfg.device >= ndev) throw Fail(TE_EINVAL, "bad device ordinal");
+  HIPCHK(hipSetDevice(cfg.device));
+
+  std::unique_ptr<Job> J(new Job());
+  J->device = cfg.device;
+  J->dev_set = true;
+  J->o = P->o; J->v = P->v; J->vp = pad_v(P->v); J->naux = P->naux; J->mem = P->mem;
+  size_t freeb = 0, total = 0;
+  HIPCHK(hipMemGetInfo(&freeb, &total));
+  J->budget = cfg.hbm_budget ? cfg.hbm_budget : (size_t)(0.9 * (double)freeb);
+  if (cfg.stream) {
+    J->s_main = (hipStream_t)cfg.stream;
+    J->own_main = false;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&J->s_main, hipStreamNonBlocking));
+    J->own_main = true;
+  }
+  HIPCHK(hipStreamCreateWithFlags(&J->s_aux, hipStreamNonBlocking));
+  for (int q = 0; q < 2; ++q) {
+    HIPCHK(hipEventCreateWithFlags(&J->ev_w[q], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&J->ev_e[q], hipEventDisableTiming));
+  }
+  HIPCHK(hipEventCreateWithFlags(&J->ev_start, hipEventDisableTiming));
+
+  const size_t o = J->o, vp = J->vp;
+  const size_t xbytes = o * vp * vp * vp * 8;
+  if (P->naux == 0) {
+    J->x_resident = true;
+  } else if (cfg.x_mode == TE_X_RESIDENT) {
+    J->x_resident = true;
+  } else if (cfg.x_mode == TE_X_ON_THE_FLY) {
+    throw Fail(TE_EINVAL, "on-the-fly slice assembly is not available in this build");
+  } else {
+    J->x_resident = xbytes <= J->budget / 2;
+    if (!J->x_resident)
+      throw Fail(TE_ENOMEM, "(vv|vo) does not fit the budget and on-the-fly assembly is off");
+  }
+
+  // sextets of 8^3 boxes
+  J->nT = (int)(vp / BOX);
+  std::vector<int> sx = sextet_list(J->nT);
+  J->nsext = (int)sx.size();
+  J->sext.alloc(sx.size() * sizeof(int), &J->used, J->budget);
+  HIPCHK(hipMemcpy(J->sext.p, sx.data(), sx.size() * sizeof(int), hipMemcpyHostToDevice));
+
+  stage(*J, *P);
+  if (cfg.validate) validate_device(*J, *P);
+  return J.release();
+}
+
+}  // namespace te
+
+using namespace te;
+
+// ------------------------------------------------------------ C ABI
+#define TE_GUARD_BEGIN try {
+#define TE_GUARD_END                                                  \
+  }                                                                   \
+  catch (const Fail &f) { return set_error(f.s, f.msg); }             \
+  catch (const std::bad_alloc &) { return set_error(TE_ENOMEM, "host allocation failed"); } \
+  catch (...) { return set_error(TE_EDEVICE, "unexpected exception"); }
+
+extern "C" {
+
+te_status te_init(const te_problem *prob, const te_config *cfg, te_job *out) {
+  TE_GUARD_BEGIN
+  if (!out) return set_error(TE_EINVAL, "out is NULL");
+  Job *J = make_job(prob, cfg);
+  *out = reinterpret_cast<te_job>(J);
+  return TE_OK;
+  TE_GUARD_END
+}
+
+static Prec to_prec(te_precision p) {
+  if (p < TE_FP64 || p > TE_BF16X2) throw Fail(TE_EINVAL, "bad precision");
+  return static_cast<Prec>(p);
+}
+
+te_status te_energy(te_job job, te_precision prec, double *e_t, double *per_triple,
+                    te_stats *st) {
+  TE_GUARD_BEGIN
+  if (!job) return set_error(TE_EINVAL, "job is NULL");
+  Job &J = *reinterpret_cast<Job *>(job);
+  Prec p = to_prec(prec);
+  HIPCHK(hipSetDevice(J.device));
+  std::vector<int> t = triple_list_host(J.o);
+  long n = (long)t.size() / 3;
+  double E = 0.0;
+  te_stats s{};
+  if (n > 0) {
+    run_triples(J, p, t.data(), n, &E, per_triple, &s);
+  }
+  if (e_t) *e_t = E;
+  if (st) *st = s;
+  return TE_OK;
+  TE_GUARD_END
+}
+
+te_status te_energy_triples(te_job job, te_precision prec, const int32_t *ijk, int64_t n,
+                            double *e_sum, double *per_triple, te_stats *st) {
+  TE_GUARD_BEGIN
+  if (!job) return set_error(TE_EINVAL, "job is NULL");
+  if (n < 0 || (n > 0 && !ijk)) return set_error(TE_EINVAL, "bad triple list");
+  Job &J = *reinterpret_cast<Job *>(job);
+  Prec p = to_prec(prec);
+  for (int64_t t = 0; t < n; ++t) {
+    int i = ijk[3 * t], j = ijk[3 * t + 1], k = ijk[3 * t + 2];
+    if (i < 0 || i > j || j > k || k >= J.o || (i == j && j == k))
+      return set_error(TE_EINVAL, "triple " + std::to_string(t) + " is not 0<=i<=j<=k<o, not all equal");
+  }
+  HIPCHK(hipSetDevice(J.device));
+  double E = 0.0;
+  te_stats s{};
+  if (n > 0) {
+    std::vector<int> t(ijk, ijk + 3 * n);
+    run_triples(J, p, t.data(), (long)n, &E, per_triple, &s);
+  }
+  if (e_sum) *e_sum = E;
+  if (st) *st = s;
+  return TE_OK;
+  TE_GUARD_END
+}
+
+te_status te_free(te_job job) {
+  TE_GUARD_BEGIN
+  if (!job) return set_error(TE_EINVAL, "job is NULL");
+  delete reinterpret_cast<Job *>(job);
+  return TE_OK;
+  TE_GUARD_END
+}
+
+int64_t te_num_triples(int32_t o) {
+  if (o < 1) return 0;
+  return (int64_t)o * (o + 1) * (o + 2) / 6 - o;
+}
+
+te_status te_triple_list(int32_t o, int32_t *ijk) {
+  if (o < 1 || !ijk) return set_error(TE_EINVAL, "need o >= 1 and a buffer");
+  std::vector<int> t = triple_list_host(o);
+  std::memcpy(ijk, t.data(), t.size() * sizeof(int));
+  return TE_OK;
+}
+
+double te_flops_per_triple(int32_t o, int32_t v) { return flops_per_triple(o, v); }
+
+const char *te_strerror(te_status s) {
+  switch (s) {
+    case TE_OK: return "ok";
+    case TE_PENDING: return "pending";
+    case TE_EINVAL: return "invalid argument";
+    case TE_ENOMEM: return "does not fit the HBM budget";
+    case TE_EDEVICE: return "HIP runtime error";
+    case TE_EBUSY: return "busy";
+    case TE_ENOTFOUND: return "unknown ticket";
+    case TE_ECANCELED: return "canceled";
+  }
+  return "unknown status";
+}
+
+const char *te_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

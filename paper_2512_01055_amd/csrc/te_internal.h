@@ -1,0 +1,87 @@
+// Internal interfaces between the C-ABI host code and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace te {
+
+// Virtual dimensions are padded to a multiple of this in every device
+// layout; padded entries are zero, so they add nothing to any contraction.
+constexpr int VPAD = 8;
+// Edge of the cubic boxes the W arrays are stored in: element (a,b,c) lives
+// at ((A*nT + B)*nT + C)*BOX^3 + (a%BOX)*BOX^2 + (b%BOX)*BOX + c%BOX.
+constexpr int BOX = 8;
+constexpr int BOX3 = BOX * BOX * BOX;
+
+inline int pad_v(int v) { return (v + VPAD - 1) / VPAD * VPAD; }
+
+enum class Prec : int { F64 = 0, F32 = 1, BF16X3 = 2, BF16X2 = 3 };
+
+// One occupied triple's W build: three GEMMs (one per lone virtual index),
+// each M = vp^2 (virtual pairs) x N = vp (lone index) x K = 2 vp + 2 o.
+struct WItem {
+  const void *Xs[3];  // slices (ix|yf) for x in i, j, k: [vp][vp][vp] each;
+                      // part p of slice q at Xs[q] + p * xps
+  const void *T2;  // t2,      layout [part][o][o][vp][vp]
+  const void *In;  // -(px|ql), layout [part][o][vp][o][o]
+  size_t xps, tps, ips;   // element stride between BF16 parts
+  void *W;         // three boxed W arrays of vp^3 each (FP64 or FP32)
+  int o, vp, i, j, k;
+  int mt, nt;      // tiles along M and N
+};
+
+// One occupied triple's energy: sum over virtual box sextets.
+struct EItem {
+  const void *W;       // as written by the W build
+  const double *K;     // (px|qy), layout [o][vp][o][vp]
+  const double *t1;    // [o][vp]
+  const double *eo;    // [o]
+  const double *ev;    // [vp]
+  const int *sext;     // packed box triples A>=B>=C: A | B<<10 | C<<20
+  double *part;        // [nsext] partial sums
+  int o, v, vp, nT, i, j, k, nsext;
+};
+
+// Per-triple reduction: e = w * sum(part[0..n)).
+struct RItem {
+  const double *part;
+  double *out;
+  int n;
+  double w;
+};
+
+// Generic FP64 "TN" product used for staging:
+//   C[row_off(m) + col_off(n)] = alpha * sum_q A[q*lda + m] * B[q*ldb + n]
+// with off(x) = (x / d) * s1 + (x % d) * s2.
+struct GemmTN {
+  const double *A, *B;
+  double *C;
+  int M, N, K;
+  long lda, ldb;
+  int rd; long rs1, rs2;
+  int cd; long cs1, cs2;
+  double alpha;
+};
+
+// Launchers (te_kernels.hip). All return the hipError_t of the launch.
+hipError_t launch_wbuild(Prec p, const WItem *d_items, const int *d_tile_item, int nitems,
+                         int tiles_per_item, long total_tiles, int bn_blocks,
+                         hipStream_t s);
+int wbuild_bm();
+int wbuild_pick_nb(int vp);
+hipError_t launch_energy(bool w_is_f64, const EItem *d_items, const int *d_blk_item,
+                         int nitems, int blks_per_item, long total_blks, hipStream_t s);
+hipError_t launch_reduce(const RItem *d_items, int nitems, hipStream_t s);
+hipError_t launch_sum(const double *x, long n, double *out, hipStream_t s);
+hipError_t launch_gemm_tn(const GemmTN &g, hipStream_t s);
+hipError_t launch_pad4(const double *src, double *dst, int d0, int d1, int d2, int d3,
+                       int p1, int p2, int p3, double scale, hipStream_t s);
+hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t s);
+hipError_t launch_to_bf16_parts(const double *src, uint16_t *dst, size_t n, int nparts,
+                                hipStream_t s);
+hipError_t launch_check(const double *x, size_t n, int *flag, hipStream_t s);
+hipError_t launch_t2_asym(const double *t2, int o, int v, double *maxdiff, double *maxabs,
+                          hipStream_t s);
+
+}  // namespace te

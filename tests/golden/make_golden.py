@@ -1,0 +1,57 @@
+"""Write stored oracle values for the GPU parity tests.
+
+Calls only the CPU oracle (and the seeded generators): nothing here comes
+from the device library.
+
+    python tests/golden/make_golden.py medium     # all 1520 triples, o=20 v=200
+    python tests/golden/make_golden.py large      # sampled triples, o=40 v=400
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2512_01055_amd.inputs import LARGE, MEDIUM, make_problem  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# triples of the large workload checked one by one: both i=j<k and i<j=k
+# kinds, first and last occupied orbitals, a generic triple
+LARGE_TRIPLES = [(0, 0, 1), (0, 1, 1), (5, 17, 33), (38, 39, 39), (2, 21, 39)]
+
+
+def run(name, shape, b_std, triples=None):
+    o, v, naux, seed = shape
+    P = make_problem(o, v, naux, seed, b_std=b_std)
+    ints = oracle.DFIntegrals(P.B_oo, P.B_ov, P.B_vv, max_cached=o if o <= 20 else 4)
+    t0 = time.time()
+    E, parts = oracle.energy(P.eps_occ, P.eps_vir, P.t1, P.t2, ints, triple_subset=triples)
+    out = {
+        "generator": "paper_2512_01055_amd.inputs.make_problem",
+        "o": o, "v": v, "naux": naux, "seed": seed, "b_std": b_std,
+        "complete": triples is None,
+        "E": E,
+        "triples": [[int(p[0]), int(p[1]), int(p[2])] for p in parts],
+        "e": [p[3] for p in parts],
+        "oracle_seconds": time.time() - t0,
+    }
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=0)
+    print(f"{path}: E = {E:.16e} over {len(parts)} triples in {out['oracle_seconds']:.1f} s")
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["medium", "large"]
+    if "medium" in which:
+        run("medium_o20_v200_seed2", MEDIUM, 0.05)
+    if "medium_phys" in which:
+        run("medium_o20_v200_seed2_phys", MEDIUM, 0.0067)
+    if "large" in which:
+        run("large_o40_v400_seed3_sample", LARGE, 0.05, LARGE_TRIPLES)
+    if "large_phys" in which:
+        run("large_o40_v400_seed3_phys_sample", LARGE, 0.0028, LARGE_TRIPLES)

@@ -1,0 +1,82 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/te.h declares, and rejects bad arguments before touching a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2512_01055_amd import te
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "te.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(te_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for required in ("te_init", "te_energy", "te_submit", "te_poll", "te_free"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(te.LIB_PATH):
+        pytest.skip("libte.so not built")
+    out = subprocess.run(["nm", "-D", "--defined-only", te.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r"\bT (te_\w+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    lib = te.lib()
+    for n in declared_functions():
+        assert hasattr(lib, n)
+
+
+def test_pure_functions():
+    lib = te.lib()
+    for o in (1, 2, 3, 6, 40, 100):
+        n = lib.te_num_triples(o)
+        assert n == o * (o + 1) * (o + 2) // 6 - o
+    assert lib.te_num_triples(0) == 0
+    t = te.triple_list(4)
+    assert len(t) == lib.te_num_triples(4)
+    assert all(i <= j <= k and not (i == j == k) for i, j, k in t)
+    assert abs(lib.te_flops_per_triple(40, 400) - 12 * 400 ** 3 * 440) < 1
+    assert lib.te_strerror(te.EINVAL) == b"invalid argument"
+
+
+def test_argument_errors_need_no_device():
+    lib = te.lib()
+    h = C.c_void_p()
+    assert lib.te_init(None, None, C.byref(h)) == te.EINVAL
+    p = te.Problem()
+    p.o, p.v, p.naux = 0, 10, 5
+    assert lib.te_init(C.byref(p), None, C.byref(h)) == te.EINVAL
+    assert b"o >= 1" in lib.te_last_error()
+    x = np.zeros(100)
+    p.o, p.v, p.naux = 2, 4, 3
+    for n in ("eps_occ", "eps_vir", "t1", "t2", "B_oo", "B_ov"):
+        setattr(p, n, x.ctypes.data)
+    assert lib.te_init(C.byref(p), None, C.byref(h)) == te.EINVAL   # B_vv missing
+    p.naux = 0
+    assert lib.te_init(C.byref(p), None, C.byref(h)) == te.EINVAL   # explicit ints missing
+    p.naux = -1
+    assert lib.te_init(C.byref(p), None, C.byref(h)) == te.EINVAL
+    e = C.c_double()
+    assert lib.te_energy(None, 0, C.byref(e), None, None) == te.EINVAL
+    assert lib.te_free(None) == te.EINVAL
+    assert lib.te_triple_list(0, None) == te.EINVAL
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(te, "_lib", None)
+    monkeypatch.setattr(te, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no fallback"):
+        te.lib()

@@ -1,0 +1,212 @@
+"""Device (T) through the C ABI against the CPU oracle.
+
+Bars (FP64 oracle as reference):
+* FP64 path: |dE| <= max(1e-8 Eh, 1e-8 |E|) as stated for the method, and
+  the tighter arithmetic bound rel <= 1e-11 on E and on every triple (FP64
+  sums of ~10^3 products carry ~1e-14 relative rounding per element).
+* FP32 / split-BF16 paths: |dE| <= max(1e-6 Eh, 1e-6 |E|); per triple the
+  same relative bar.
+The relative reading is needed because the stated generators give |E| far
+above 1 Eh; the physical-scale cases (smaller B spread, |E| < 1 Eh) apply
+the absolute bars literally.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_01055_amd.inputs import LARGE, MEDIUM, make_problem, sample_triples
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL = {"fp64": 1e-8, "fp32": 1e-6, "bf16x3": 1e-6, "bf16x2": 1e-6}
+PRECS = ["fp64", "fp32", "bf16x3", "bf16x2"]
+
+
+def _te():
+    from paper_2512_01055_amd import te
+    return te
+
+
+def bar(prec, E_ref):
+    return max(TOL[prec], TOL[prec] * abs(E_ref))
+
+
+_ORACLE_CACHE = {}
+
+
+def oracle_parts(key, P, triples=None):
+    if key not in _ORACLE_CACHE:
+        ints = oracle.DFIntegrals(P.B_oo, P.B_ov, P.B_vv, max_cached=max(4, P.o))
+        E, parts = oracle.energy(P.eps_occ, P.eps_vir, P.t1, P.t2, ints, triple_subset=triples)
+        _ORACLE_CACHE[key] = (E, np.array([p[3] for p in parts]),
+                              np.array([p[:3] for p in parts], dtype=np.int32))
+    return _ORACLE_CACHE[key]
+
+
+# (name, o, v, naux, seed, b_std): the small workload shape, several tiles with
+# ragged tails in both GEMM dimensions, v not a multiple of 8, and a
+# physical-scale variant where |E| < 1 Eh
+SMALL_CASES = [
+    ("small", 6, 30, 90, 1, 0.05),
+    ("ragged", 7, 72, 40, 17, 0.05),
+    ("pad", 5, 61, 30, 18, 0.05),
+    ("o2", 2, 24, 20, 19, 0.05),
+    ("physical", 6, 30, 90, 1, 0.0375),
+]
+
+
+@pytest.mark.parametrize("case", SMALL_CASES, ids=[c[0] for c in SMALL_CASES])
+@pytest.mark.parametrize("prec", PRECS)
+def test_all_triples_match_oracle(case, prec):
+    name, o, v, naux, seed, std = case
+    print(f"\n[case {name} o={o} v={v} naux={naux} seed={seed} prec={prec}]", flush=True)
+    P = make_problem(o, v, naux, seed, b_std=std)
+    E_ref, e_ref, _ = oracle_parts(name, P)
+    te = _te()
+    with te.Job(P, device=0) as job:
+        E, st, pt = job.energy(prec, per_triple=True)
+    dE = abs(E - E_ref)
+    print(f"E dev {E:.15e} oracle {E_ref:.15e} |dE| {dE:.3e} rel {dE / abs(E_ref):.3e}")
+    assert st["n_triples"] == len(e_ref)
+    assert dE <= bar(prec, E_ref)
+    if prec == "fp64":
+        assert dE <= 1e-11 * abs(E_ref)
+        assert np.all(np.abs(pt - e_ref) <= 1e-11 * np.abs(e_ref) + 1e-300)
+    else:
+        assert np.all(np.abs(pt - e_ref) <= TOL[prec] * np.maximum(np.abs(e_ref), 1.0))
+
+
+def test_medium_all_triples_fp64_and_reduced():
+    path = os.path.join(GOLDEN, "medium_o20_v200_seed2.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle values for o=20 v=200 are missing")
+    g = json.load(open(path))
+    P = make_problem(*MEDIUM, b_std=g["b_std"])
+    te = _te()
+    e_ref = np.array(g["e"])
+    with te.Job(P, device=0) as job:
+        for prec in PRECS:
+            print(f"\n[medium o=20 v=200 prec={prec}]", flush=True)
+            E, st, pt = job.energy(prec, per_triple=True)
+            dE = abs(E - g["E"])
+            print(f"E dev {E:.15e} oracle {g['E']:.15e} |dE| {dE:.3e} rel {dE / abs(g['E']):.3e} "
+                  f"{st['tflops']:.2f} TFLOP/s")
+            assert dE <= bar(prec, g["E"])
+            if prec == "fp64":
+                assert dE <= 1e-11 * abs(g["E"])
+                assert np.max(np.abs(pt - e_ref) / np.abs(e_ref)) <= 1e-11
+            else:
+                assert np.max(np.abs(pt - e_ref) / np.abs(e_ref)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_large_sampled_triples(prec):
+    """Full-size o=40 v=400 job in the configuration the benchmark times;
+    triples checked one by one against stored oracle values."""
+    path = os.path.join(GOLDEN, "large_o40_v400_seed3_sample.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle values for o=40 v=400 are missing")
+    g = json.load(open(path))
+    key = ("large", g["b_std"])
+    te = _te()
+    if key not in _JOBS:
+        print("\n[large o=40 v=400: staging]", flush=True)
+        P = make_problem(*LARGE, b_std=g["b_std"])
+        _JOBS.clear()
+        _JOBS[key] = te.Job(P, device=0)
+    job = _JOBS[key]
+    print(f"[large o=40 v=400 prec={prec}]", flush=True)
+    Es, pt, st = job.energy_triples(g["triples"], prec)
+    e_ref = np.array(g["e"])
+    rel = np.abs(pt - e_ref) / np.abs(e_ref)
+    print(f"per-triple rel max {rel.max():.3e}; {st['tflops']:.2f} TFLOP/s over {len(pt)} triples")
+    assert np.all(rel <= (1e-11 if prec == "fp64" else TOL[prec]))
+    if prec == "bf16x2":
+        _JOBS.clear()
+
+
+_JOBS = {}
+
+
+def test_host_and_device_inputs_are_bitwise_equal():
+    import torch
+    P = make_problem(5, 40, 30, 23)
+    te = _te()
+    with te.Job(P, device=0) as job:
+        E_h, _, pt_h = job.energy("fp64", per_triple=True)
+    dev = {n: torch.from_numpy(getattr(P, n)).cuda() for n in
+           ("eps_occ", "eps_vir", "t1", "t2", "B_oo", "B_ov", "B_vv")}
+    dev.update(o=P.o, v=P.v, naux=P.naux)
+
+    class Obj:
+        pass
+    Q = Obj()
+    for k_, x in dev.items():
+        setattr(Q, k_, x)
+    with te.Job(Q, device=0) as job:
+        E_d, _, pt_d = job.energy("fp64", per_triple=True)
+    assert E_h == E_d
+    assert np.array_equal(pt_h, pt_d)
+
+
+def test_explicit_integrals_match_df():
+    P = make_problem(4, 33, 20, 24)
+    ovvv, ovoo, ovov = oracle.integrals_from_df(P.B_oo, P.B_ov, P.B_vv)
+    te = _te()
+    with te.Job(P, device=0) as job:
+        E_df, _ = job.energy("fp64")
+    ex = dict(eps_occ=P.eps_occ, eps_vir=P.eps_vir, t1=P.t1, t2=P.t2, ovvv=ovvv, ovoo=ovoo,
+              ovov=ovov)
+
+    class Obj:
+        pass
+    Q = Obj()
+    for k_, x in ex.items():
+        setattr(Q, k_, x)
+    Q.o, Q.v, Q.naux = P.o, P.v, 0
+    with te.Job(Q, device=0, explicit=True) as job:
+        E_ex, _ = job.energy("fp64")
+    assert abs(E_ex - E_df) <= 1e-12 * abs(E_df)
+
+
+def test_reproducible_and_subset_consistent():
+    P = make_problem(6, 48, 30, 25)
+    te = _te()
+    with te.Job(P, device=0) as job:
+        for prec in ("fp64", "bf16x3"):
+            E1, _, pt1 = job.energy(prec, per_triple=True)
+            E2, _, pt2 = job.energy(prec, per_triple=True)
+            assert E1 == E2 and np.array_equal(pt1, pt2)
+            allt = te.triple_list(P.o)
+            sub = sample_triples(P.o, 9, 3)
+            idx = [int(np.nonzero((allt == s).all(1))[0][0]) for s in sub]
+            _, ps, _ = job.energy_triples(sub, prec)
+            assert np.array_equal(ps, pt1[idx])       # batching does not change a triple
+
+
+def test_validation_rejects_bad_inputs():
+    te = _te()
+    P = make_problem(3, 16, 10, 26)
+    P.t2 = P.t2.copy()
+    P.t2[0, 1, 2, 3] += 1e-3                       # breaks t_ij^ab = t_ji^ba
+    with pytest.raises(te.TeError) as ei:
+        te.Job(P, device=0, validate=True)
+    assert ei.value.status == te.EINVAL
+    P = make_problem(3, 16, 10, 26)
+    P.B_vv = P.B_vv.copy()
+    P.B_vv[0, 0, 0] = np.nan
+    with pytest.raises(te.TeError) as ei:
+        te.Job(P, device=0, validate=True)
+    assert ei.value.status == te.EINVAL
+
+
+def test_budget_too_small_is_enomem():
+    te = _te()
+    P = make_problem(4, 64, 20, 27)
+    with pytest.raises(te.TeError) as ei:
+        te.Job(P, device=0, hbm_budget=1 << 20)
+    assert ei.value.status == te.ENOMEM
