@@ -99,6 +99,12 @@ typedef struct te_stats {
   int64_t n_triples;     /* occupied triples evaluated                           */
   double stage_seconds;  /* part of `seconds` spent preparing operands           */
   double assemble_flops; /* on-the-fly mode: flops spent assembling slices       */
+  /* Device time of the kernels, from HIP events recorded around each launch
+   * on the stream it runs on: the W build (MFMA) and the energy consumer. */
+  double w_kernel_seconds;
+  int64_t w_launches;
+  double e_kernel_seconds;
+  int64_t e_launches;
 } te_stats;
 
 typedef struct te_job_s *te_job;

@@ -31,31 +31,103 @@ te_status set_error(te_status s, const std::string &m) {
   return s;
 }
 
+// ------------------------------------------------------------ Arena
+void Arena::init(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess)
+    throw Fail(TE_ENOMEM, "arena hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+  base = (char *)p;
+  cap = bytes;
+  used = 0;
+  free_.clear();
+  free_[0] = bytes;
+}
+void Arena::destroy() {
+  if (base) (void)hipFree(base);
+  base = nullptr;
+  cap = used = 0;
+  free_.clear();
+}
+void *Arena::take(size_t n) {
+  std::lock_guard<std::mutex> lk(mu);
+  n = (n + 255) & ~(size_t)255;
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second >= n) {
+      size_t off = it->first, len = it->second;
+      free_.erase(it);
+      if (len > n) free_[off + n] = len - n;
+      used += n;
+      return base + off;
+    }
+  }
+  return nullptr;
+}
+void Arena::give(void *p, size_t n) {
+  std::lock_guard<std::mutex> lk(mu);
+  n = (n + 255) & ~(size_t)255;
+  size_t off = (size_t)((char *)p - base);
+  used -= n;
+  auto it = free_.emplace(off, n).first;
+  auto nx = std::next(it);
+  if (nx != free_.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    free_.erase(nx);
+  }
+  if (it != free_.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      free_.erase(it);
+    }
+  }
+}
+size_t Arena::largest_free() {
+  std::lock_guard<std::mutex> lk(mu);
+  size_t m = 0;
+  for (auto &kv : free_) m = std::max(m, kv.second);
+  return m;
+}
+
 // ------------------------------------------------------------ DBuf
 DBuf::~DBuf() { release(); }
 void DBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (arena) arena->give(p, bytes);
+    else (void)hipFree(p);
+  }
   if (acct) *acct -= bytes;
   p = nullptr;
   bytes = 0;
   acct = nullptr;
+  arena = nullptr;
 }
-void DBuf::alloc(size_t n, size_t *account, size_t budget) {
+void DBuf::alloc(size_t n, size_t *account, size_t budget, Arena *ar) {
   release();
   if (n == 0) n = 16;
   if (account && *account + n > budget)
     throw Fail(TE_ENOMEM, "device allocation of " + std::to_string(n) +
                               " bytes exceeds the HBM budget (" + std::to_string(*account) +
                               " of " + std::to_string(budget) + " in use)");
-  hipError_t e = hipMalloc(&p, n);
-  if (e != hipSuccess) {
-    p = nullptr;
-    throw Fail(TE_ENOMEM, "hipMalloc(" + std::to_string(n) + "): " + hipGetErrorString(e));
+  if (ar) {
+    p = ar->take(n);
+    if (!p)
+      throw Fail(TE_ENOMEM, "arena has no free range of " + std::to_string(n) + " bytes");
+  } else {
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Fail(TE_ENOMEM, "hipMalloc(" + std::to_string(n) + "): " + hipGetErrorString(e));
+    }
   }
   bytes = n;
   acct = account;
+  arena = ar;
   if (acct) *acct += n;
 }
+
+void jalloc(Job &J, DBuf &b, size_t n) { b.alloc(n, &J.used, J.budget, J.arena); }
 
 // ------------------------------------------------------------ triples
 std::vector<int> triple_list_host(int o) {
@@ -84,7 +156,7 @@ static size_t out_size(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
 // ------------------------------------------------------------ staging
 static void copy_in(Job &J, const double *src, size_t n, DBuf &dst, bool device_src) {
-  dst.alloc(n * sizeof(double), &J.used, J.budget);
+  jalloc(J, dst, n * sizeof(double));
   HIPCHK(hipMemcpyAsync(dst.p, src, n * sizeof(double),
                         device_src ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, J.s_main));
 }
@@ -99,7 +171,7 @@ static const double *device_view(Job &J, const double *src, size_t n, DBuf &tmp)
 static void stage_padded(Job &J, const double *src, int d0, int d1, int d2, int d3, int p1,
                          int p2, int p3, double scale, DBuf &dst) {
   size_t n = (size_t)d0 * p1 * p2 * p3;
-  dst.alloc(n * sizeof(double), &J.used, J.budget);
+  jalloc(J, dst, n * sizeof(double));
   HIPCHK(hipMemsetAsync(dst.p, 0, n * sizeof(double), J.s_main));
   DBuf tmp;
   const double *s = device_view(J, src, (size_t)d0 * d1 * d2 * d3, tmp);
@@ -136,7 +208,7 @@ static void stage(Job &J, const te_problem &P) {
   {
     DBuf tmp;
     const double *ev = device_view(J, P.eps_vir, v, tmp);
-    J.ev.alloc((size_t)vp * 8, &J.used, J.budget);
+    jalloc(J, J.ev, (size_t)vp * 8);
     HIPCHK(hipMemsetAsync(J.ev.p, 0, (size_t)vp * 8, s));
     HIPCHK(hipMemcpyAsync(J.ev.p, ev, (size_t)v * 8, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -158,17 +230,17 @@ static void stage(Job &J, const te_problem &P) {
     J.Boo = device_view(J, P.B_oo, (size_t)naux * o * o, J.Boo_own);
     J.Bvv = device_view(J, P.B_vv, (size_t)naux * v * v, J.Bvv_own);
     // K[p][x][q][y] = (px|qy), for V (Eq. 3)
-    J.K.alloc((size_t)o * vp * o * vp * 8, &J.used, J.budget);
+    jalloc(J, J.K, (size_t)o * vp * o * vp * 8);
     HIPCHK(hipMemsetAsync(J.K.p, 0, J.K.bytes, s));
     gemm_stage(J, J.Bov, (long)o * v, J.Bov, (long)o * v, o * v, o * v, naux, v,
                (long)vp * o * vp, (long)o * vp, v, vp, 1, 1.0, J.K.as<double>());
     // In[p][x][q][l] = -(px|ql), the occupied term of Eq. 2 with its sign
-    J.In.alloc((size_t)o * vp * o * o * 8, &J.used, J.budget);
+    jalloc(J, J.In, (size_t)o * vp * o * o * 8);
     HIPCHK(hipMemsetAsync(J.In.p, 0, J.In.bytes, s));
     gemm_stage(J, J.Bov, (long)o * v, J.Boo, (long)o * o, o * v, o * o, naux, v,
                (long)vp * o * o, (long)o * o, o * o, 0, 1, -1.0, J.In.as<double>());
     if (J.x_resident) {
-      J.X.alloc(nX * 8, &J.used, J.budget);
+      jalloc(J, J.X, nX * 8);
       std::vector<int> all(o);
       for (int p = 0; p < o; ++p) all[p] = p;
       stage_df_slices(J, all.data(), o, J.X.as<double>(), (size_t)vp * vp * vp);
@@ -222,27 +294,31 @@ const Operands &ensure_prec(Job &J, Prec p) {
   const size_t nT2 = (size_t)o * o * vp * vp;
   const size_t nIn = (size_t)o * vp * o * o;
   const size_t nX = J.X.p ? (size_t)o * vp * vp * vp : 0;
+  if (p != Prec::F64 && !J.X.p && J.x_resident)
+    throw Fail(TE_EINVAL, "the FP64 (vv|vo) copy was released; precision cannot change");
   if (p == Prec::F64) {
+    if (!J.X.p && J.x_resident)
+      throw Fail(TE_EINVAL, "the FP64 (vv|vo) copy was released; precision cannot change");
     op.X = J.X.p; op.T2 = J.t2; op.In = J.In.p;
     op.xps = nX; op.tps = nT2; op.ips = nIn;
   } else if (p == Prec::F32) {
-    op.T2_own.alloc(nT2 * 4, &J.used, J.budget);
-    op.In_own.alloc(nIn * 4, &J.used, J.budget);
+    jalloc(J, op.T2_own, nT2 * 4);
+    jalloc(J, op.In_own, nIn * 4);
     HIPCHK(launch_to_f32(J.t2, op.T2_own.as<float>(), nT2, J.s_main));
     HIPCHK(launch_to_f32(J.In.as<double>(), op.In_own.as<float>(), nIn, J.s_main));
     if (nX) {
-      op.X_own.alloc(nX * 4, &J.used, J.budget);
+      jalloc(J, op.X_own, nX * 4);
       HIPCHK(launch_to_f32(J.X.as<double>(), op.X_own.as<float>(), nX, J.s_main));
     }
     op.X = op.X_own.p; op.T2 = op.T2_own.p; op.In = op.In_own.p;
     op.xps = nX; op.tps = nT2; op.ips = nIn;
   } else {
-    op.T2_own.alloc(nT2 * 2 * 3, &J.used, J.budget);
-    op.In_own.alloc(nIn * 2 * 3, &J.used, J.budget);
+    jalloc(J, op.T2_own, nT2 * 2 * 3);
+    jalloc(J, op.In_own, nIn * 2 * 3);
     HIPCHK(launch_to_bf16_parts(J.t2, op.T2_own.as<uint16_t>(), nT2, 3, J.s_main));
     HIPCHK(launch_to_bf16_parts(J.In.as<double>(), op.In_own.as<uint16_t>(), nIn, 3, J.s_main));
     if (nX) {
-      op.X_own.alloc(nX * 2 * 3, &J.used, J.budget);
+      jalloc(J, op.X_own, nX * 2 * 3);
       HIPCHK(launch_to_bf16_parts(J.X.as<double>(), op.X_own.as<uint16_t>(), nX, 3, J.s_main));
     }
     op.X = op.X_own.p; op.T2 = op.T2_own.p; op.In = op.In_own.p;
@@ -254,6 +330,29 @@ const Operands &ensure_prec(Job &J, Prec p) {
 }
 
 // ------------------------------------------------------------ execution
+// Pairs of events bracketing each launch of one kernel.
+struct TimingEvents {
+  std::vector<hipEvent_t> start, stop;
+  explicit TimingEvents(long n) : start(n, nullptr), stop(n, nullptr) {
+    for (long q = 0; q < n; ++q) {
+      HIPCHK(hipEventCreate(&start[q]));
+      HIPCHK(hipEventCreate(&stop[q]));
+    }
+  }
+  ~TimingEvents() {
+    for (auto e : start) if (e) (void)hipEventDestroy(e);
+    for (auto e : stop) if (e) (void)hipEventDestroy(e);
+  }
+  double total() const {  // seconds; call after the stream has been synchronised
+    double s = 0.0;
+    for (size_t q = 0; q < start.size(); ++q) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, start[q], stop[q]) == hipSuccess) s += ms * 1e-3;
+    }
+    return s;
+  }
+};
+
 double flops_per_triple(int o, int v) { return 12.0 * (double)v * v * v * ((double)v + o); }
 
 static int batch_size(const Job &J, Prec p, long ntr) {
@@ -276,7 +375,7 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
   auto t0 = std::chrono::steady_clock::now();
   const Operands &op = ensure_prec(J, p);
   auto t1 = std::chrono::steady_clock::now();
-  if (!J.X.p) throw Fail(TE_EINVAL, "(vv|vo) slices are not resident");
+  if (!op.X) throw Fail(TE_EINVAL, "(vv|vo) slices are not resident");
 
   const int o = J.o, vp = J.vp;
   const int bm = wbuild_bm();
@@ -332,17 +431,23 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
   HIPCHK(hipStreamWaitEvent(J.s_aux, J.ev_start, 0));
 
   const bool f64 = p == Prec::F64;
+  // timing events around every launch (device time of each kernel)
+  TimingEvents tw(nbatch), te_(nbatch);
   for (long b = 0; b < nbatch; ++b) {
     const int slot = (int)(b & 1);
     const long first = b * B;
     const int cnt = (int)std::min<long>(B, ntr - first);
     if (b >= 2) HIPCHK(hipStreamWaitEvent(J.s_aux, J.ev_e[slot], 0));
+    HIPCHK(hipEventRecord(tw.start[b], J.s_aux));
     HIPCHK(launch_wbuild(p, witems.as<WItem>() + first, nullptr, cnt, tiles, (long)cnt * tiles,
                          nbk, J.s_aux));
+    HIPCHK(hipEventRecord(tw.stop[b], J.s_aux));
     HIPCHK(hipEventRecord(J.ev_w[slot], J.s_aux));
     HIPCHK(hipStreamWaitEvent(J.s_main, J.ev_w[slot], 0));
+    HIPCHK(hipEventRecord(te_.start[b], J.s_main));
     HIPCHK(launch_energy(f64, eitems.as<EItem>() + first, nullptr, cnt, J.nsext,
                          (long)cnt * J.nsext, J.s_main));
+    HIPCHK(hipEventRecord(te_.stop[b], J.s_main));
     HIPCHK(launch_reduce(ritems.as<RItem>() + first, cnt, J.s_main));
     HIPCHK(hipEventRecord(J.ev_e[slot], J.s_main));
   }
@@ -361,6 +466,10 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
     st->flops = (double)ntr * flops_per_triple(o, J.v);
     st->tflops = st->flops / std::max(st->seconds, 1e-12) / 1e12;
     st->assemble_flops = 0.0;
+    st->w_kernel_seconds = tw.total();
+    st->w_launches = nbatch;
+    st->e_kernel_seconds = te_.total();
+    st->e_launches = nbatch;
   }
 }
 
@@ -405,7 +514,25 @@ static void check_host_values(const te_problem &P) {
     throw Fail(TE_EINVAL, "input holds a non-finite value");
 }
 
-Job *make_job(const te_problem *P, const te_config *cfg_in) {
+int out_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
+
+size_t job_footprint(int o, int v, int naux, Prec p) {
+  const size_t O = o, V = v, VP = pad_v(v), N = naux;
+  const size_t nT = VP / BOX, nsext = nT * (nT + 1) * (nT + 2) / 6;
+  const size_t nt = (size_t)te_num_triples(o);
+  size_t b = 8 * (O + VP + O * VP) + 8 * O * O * VP * VP * 2 + 8 * O * VP * O * O;
+  b += 4 * nsext + 8 * nt + 8;
+  // staging temporaries: unpadded host copies and the factors
+  b += 8 * (O + V + O * V + O * O * V * V);
+  b += naux > 0 ? 8 * N * (O * V + O * O + V * V) : 8 * (O * V * V * V + O * V * O * O + O * V * O * V);
+  const size_t nX = O * VP * VP * VP, nT2 = O * O * VP * VP, nIn = O * VP * O * O;
+  b += 8 * nX;
+  if (p == Prec::F32) b += 4 * (nX + nT2 + nIn);
+  if (p == Prec::BF16X3 || p == Prec::BF16X2) b += 6 * (nX + nT2 + nIn);
+  return b + 32 * 256;
+}
+
+Job *make_job(const te_problem *P, const te_config *cfg_in, const JobOpts *opts) {
   check_problem(P);
   te_config cfg{};
   if (cfg_in) cfg = *cfg_in;
@@ -421,22 +548,35 @@ Job *make_job(const te_problem *P, const te_config *cfg_in) {
   J->device = cfg.device;
   J->dev_set = true;
   J->o = P->o; J->v = P->v; J->vp = pad_v(P->v); J->naux = P->naux; J->mem = P->mem;
-  size_t freeb = 0, total = 0;
-  HIPCHK(hipMemGetInfo(&freeb, &total));
-  J->budget = cfg.hbm_budget ? cfg.hbm_budget : (size_t)(0.9 * (double)freeb);
-  if (cfg.stream) {
+  if (opts && opts->arena) J->arena = opts->arena;
+  if (opts && opts->budget) {
+    J->budget = opts->budget;
+  } else if (cfg.hbm_budget) {
+    J->budget = cfg.hbm_budget;
+  } else {
+    size_t freeb = 0, total = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &total));
+    J->budget = (size_t)(0.9 * (double)freeb);
+  }
+  if (opts && opts->stream) {
+    J->s_main = opts->stream;
+    J->own_main = false;
+    J->own_aux = false;
+  } else if (cfg.stream) {
     J->s_main = (hipStream_t)cfg.stream;
     J->own_main = false;
   } else {
     HIPCHK(hipStreamCreateWithFlags(&J->s_main, hipStreamNonBlocking));
     J->own_main = true;
   }
-  HIPCHK(hipStreamCreateWithFlags(&J->s_aux, hipStreamNonBlocking));
-  for (int q = 0; q < 2; ++q) {
-    HIPCHK(hipEventCreateWithFlags(&J->ev_w[q], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&J->ev_e[q], hipEventDisableTiming));
+  if (J->own_aux) {
+    HIPCHK(hipStreamCreateWithFlags(&J->s_aux, hipStreamNonBlocking));
+    for (int q = 0; q < 2; ++q) {
+      HIPCHK(hipEventCreateWithFlags(&J->ev_w[q], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&J->ev_e[q], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&J->ev_start, hipEventDisableTiming));
   }
-  HIPCHK(hipEventCreateWithFlags(&J->ev_start, hipEventDisableTiming));
 
   const size_t o = J->o, vp = J->vp;
   const size_t xbytes = o * vp * vp * vp * 8;
@@ -456,11 +596,20 @@ Job *make_job(const te_problem *P, const te_config *cfg_in) {
   J->nT = (int)(vp / BOX);
   std::vector<int> sx = sextet_list(J->nT);
   J->nsext = (int)sx.size();
-  J->sext.alloc(sx.size() * sizeof(int), &J->used, J->budget);
-  HIPCHK(hipMemcpy(J->sext.p, sx.data(), sx.size() * sizeof(int), hipMemcpyHostToDevice));
+  jalloc(*J, J->sext, sx.size() * sizeof(int));
+  HIPCHK(hipMemcpyAsync(J->sext.p, sx.data(), sx.size() * sizeof(int), hipMemcpyHostToDevice,
+                        J->s_main));
+  HIPCHK(hipStreamSynchronize(J->s_main));
 
   stage(*J, *P);
   if (cfg.validate) validate_device(*J, *P);
+  if (opts) {
+    ensure_prec(*J, opts->prec);
+    if (opts->drop_fp64_x && opts->prec != Prec::F64) {
+      J->X.release();
+      J->op[(int)Prec::F64].ready = false;
+    }
+  }
   return J.release();
 }
 

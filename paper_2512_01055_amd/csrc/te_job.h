@@ -2,7 +2,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -22,16 +24,34 @@ void hip_check(hipError_t e, const char *what, int line);
 
 te_status set_error(te_status s, const std::string &m);
 
-// Device allocation charged against a job's HBM budget.
+// One device allocation carved up on the host: first fit over a free list,
+// 256-byte granules. Freeing never touches the device, so a server can
+// recycle memory of finished jobs while other work is in flight (it frees a
+// range only after the work that used it has completed).
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0, used = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  std::mutex mu;
+  void init(size_t bytes);          // one hipMalloc of the whole budget
+  void destroy();
+  void *take(size_t n);              // nullptr when no free range fits
+  void give(void *p, size_t n);
+  size_t largest_free();
+};
+
+// Device allocation charged against a job's HBM budget (from an arena when
+// one is given, else straight from hipMalloc).
 struct DBuf {
   void *p = nullptr;
   size_t bytes = 0;
   size_t *acct = nullptr;
+  Arena *arena = nullptr;
   DBuf() = default;
   DBuf(const DBuf &) = delete;
   DBuf &operator=(const DBuf &) = delete;
   ~DBuf();
-  void alloc(size_t n, size_t *account, size_t budget);
+  void alloc(size_t n, size_t *account, size_t budget, Arena *ar = nullptr);
   void release();
   template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
 };
@@ -53,6 +73,8 @@ struct Job {
   hipEvent_t ev_w[2] = {nullptr, nullptr}, ev_e[2] = {nullptr, nullptr}, ev_start = nullptr;
   size_t budget = 0, used = 0;
   bool x_resident = true;
+  Arena *arena = nullptr;      // server jobs allocate from the server's arena
+  bool own_aux = true;         // false: no second stream / events (server jobs)
 
   DBuf eo, ev, t1, K, In, X, t2_own, sext;
   const double *t2 = nullptr;
@@ -63,7 +85,19 @@ struct Job {
   ~Job();
 };
 
-Job *make_job(const te_problem *P, const te_config *cfg);
+// Optional knobs for jobs created by the server.
+struct JobOpts {
+  Arena *arena = nullptr;
+  hipStream_t stream = nullptr;   // staging stream (not owned)
+  size_t budget = 0;              // 0: from te_config / free memory
+  bool drop_fp64_x = false;       // free the FP64 (vv|vo) copy after converting
+  Prec prec = Prec::F64;          // precision staged eagerly
+};
+
+Job *make_job(const te_problem *P, const te_config *cfg, const JobOpts *opts = nullptr);
+void jalloc(Job &J, DBuf &b, size_t n);
+size_t job_footprint(int o, int v, int naux, Prec p);
+int out_bytes(Prec p);
 const Operands &ensure_prec(Job &J, Prec p);
 void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double *per_triple,
                  te_stats *st);

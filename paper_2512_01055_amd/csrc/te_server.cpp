@@ -1,23 +1,645 @@
-// Serving runtime: placeholder entry points until the packed server lands.
+// Continuous-batching (T) server.
+//
+// Jobs of mixed (o, v) are queued by te_submit, admitted when their HBM
+// footprint fits a server-wide arena, staged by a staging thread (integral
+// assembly and precision copies on their own stream, overlapping the compute
+// of resident jobs), and their occupied triples are packed with those of every
+// other resident job of the same precision into shared launches: one W-build
+// launch and one energy launch per round, mapping tiles and sextet blocks to
+// (job, triple) items. Two rounds are in flight at once (two scratch slots).
+// A job finishes with a fixed-order sum of its per-triple partials, so its
+// result is bitwise the one te_energy computes for it alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
 #include "te.h"
+#include "te_internal.h"
 #include "te_job.h"
+
+namespace te {
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+// Host copy of a submitted problem (te_submit returns before staging).
+struct HostCopy {
+  te_problem p{};
+  std::vector<double> a[10];
+  void take(const te_problem &src) {
+    p = src;
+    p.mem = TE_MEM_HOST;
+    const size_t o = src.o, v = src.v, n = src.naux;
+    auto cp = [&](int slot, const double *x, size_t cnt, const double **dst) {
+      if (!x) { *dst = nullptr; return; }
+      a[slot].assign(x, x + cnt);
+      *dst = a[slot].data();
+    };
+    cp(0, src.eps_occ, o, &p.eps_occ);
+    cp(1, src.eps_vir, v, &p.eps_vir);
+    cp(2, src.t1, o * v, &p.t1);
+    cp(3, src.t2, o * o * v * v, &p.t2);
+    if (n > 0) {
+      cp(4, src.B_oo, n * o * o, &p.B_oo);
+      cp(5, src.B_ov, n * o * v, &p.B_ov);
+      cp(6, src.B_vv, n * v * v, &p.B_vv);
+      p.ovvv = p.ovoo = p.ovov = nullptr;
+    } else {
+      cp(7, src.ovvv, o * v * v * v, &p.ovvv);
+      cp(8, src.ovoo, o * v * o * o, &p.ovoo);
+      cp(9, src.ovov, o * v * o * v, &p.ovov);
+      p.B_oo = p.B_ov = p.B_vv = nullptr;
+    }
+  }
+  void drop() {
+    for (auto &x : a) std::vector<double>().swap(x);
+  }
+};
+
+enum class JS { Queued, Staging, Resident, Finishing, Done };
+
+struct SJob {
+  uint64_t ticket = 0;
+  Prec prec = Prec::F64;
+  HostCopy hc;
+  int o = 0, v = 0, naux = 0;
+  size_t footprint = 0;
+  std::unique_ptr<Job> job;
+  std::vector<int> trip;
+  long ntr = 0, next = 0;
+  DBuf eout, esum;
+  double *h_E = nullptr;
+  hipEvent_t done_ev = nullptr;
+  JS state = JS::Queued;
+  te_status status = TE_PENDING;
+  std::string err;
+  double E = 0.0;
+  te_stats st{};
+  clk::time_point t_submit, t_admit, t_staged, t_done;
+  uint64_t retry_after = 0;  // requeued after a fragmented-arena miss
+};
+
+// Per-round limits. te_submit rejects jobs whose single triple would
+// exceed them, so every round can hold at least one item.
+constexpr int MAX_ITEMS = 4096;
+constexpr long MAX_TILES = 262144;
+constexpr long MAX_BLKS = 4L << 20;
+
+struct Slot {
+  DBuf W, part, witems, eitems, ritems, tmap, bmap;
+  WItem *h_wi = nullptr;
+  EItem *h_ei = nullptr;
+  RItem *h_ri = nullptr;
+  int *h_tmap = nullptr, *h_bmap = nullptr;
+  hipEvent_t ev_w = nullptr, ev_e = nullptr;
+  bool busy = false;
+};
+
+}  // namespace
+
+struct ServerImpl {
+  int device = 0;
+  size_t budget = 0, wcap = 0;
+  int max_resident = 64, max_queued = 4096;
+  Arena arena;
+  hipStream_t s_w = nullptr, s_e = nullptr, s_stage = nullptr;
+  Slot slot[2];
+  long round = 0;
+
+  std::mutex mu;
+  std::condition_variable cv;       // wakes the scheduler and the stager
+  std::condition_variable cv_done;  // wakes te_wait callers
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::deque<SJob *> queue;         // submitted, not yet admitted
+  std::list<SJob *> resident;       // staged (or staging), admission order
+  std::unordered_map<uint64_t, std::unique_ptr<SJob>> jobs;
+  size_t reserved = 0;              // footprints of admitted jobs
+  uint64_t retired = 0;             // jobs retired so far
+  std::thread sched, stager;
+  std::string fatal;
+
+  void start();
+  void shutdown();
+  void stage_loop();
+  void sched_loop();
+  bool launch_round();
+  void retire();
+  void finish_job(SJob *j, te_status s, const std::string &msg);
+};
+
+void ServerImpl::finish_job(SJob *j, te_status s, const std::string &msg) {
+  j->status = s;
+  j->err = msg;
+  j->state = JS::Done;
+  j->t_done = clk::now();
+}
+
+// Staging thread: admits jobs in arrival order while their footprint fits.
+void ServerImpl::stage_loop() {
+  HIPCHK(hipSetDevice(device));
+  for (;;) {
+    SJob *j = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] {
+        if (stop) return true;
+        if (queue.empty()) return false;
+        if ((int)resident.size() >= max_resident) return false;
+        if (queue.front()->retry_after > retired) return false;
+        return reserved + queue.front()->footprint <= arena.cap;
+      });
+      if (stop) return;
+      j = queue.front();
+      queue.pop_front();
+      j->state = JS::Staging;
+      j->t_admit = clk::now();
+      reserved += j->footprint;
+      resident.push_back(j);
+    }
+    te_status s = TE_OK;
+    std::string msg;
+    try {
+      JobOpts jo;
+      jo.arena = &arena;
+      jo.stream = s_stage;
+      jo.budget = j->footprint;
+      jo.drop_fp64_x = true;
+      jo.prec = j->prec;
+      te_config cfg{};
+      cfg.device = device;
+      cfg.x_mode = TE_X_RESIDENT;
+      j->job.reset(make_job(&j->hc.p, &cfg, &jo));
+      Job &J = *j->job;
+      jalloc(J, j->eout, (size_t)j->ntr * 8);
+      jalloc(J, j->esum, 8);
+      HIPCHK(hipStreamSynchronize(s_stage));
+      J.s_main = nullptr;  // the job's device work is tracked by server events from now on
+      j->hc.drop();
+    } catch (const Fail &f) {
+      s = f.s;
+      msg = f.msg;
+    } catch (...) {
+      s = TE_EDEVICE;
+      msg = "staging failed";
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    j->t_staged = clk::now();
+    if (s == TE_ENOMEM && resident.size() > 1) {
+      // the arena is fragmented by other resident jobs: retry after one retires
+      resident.remove(j);
+      j->eout.release();
+      j->esum.release();
+      j->job.reset();
+      reserved -= j->footprint;
+      j->state = JS::Queued;
+      j->retry_after = retired + 1;
+      queue.push_front(j);
+      cv.notify_all();
+      continue;
+    }
+    if (s != TE_OK) {
+      resident.remove(j);
+      j->eout.release();
+      j->esum.release();
+      j->job.reset();
+      reserved -= j->footprint;
+      finish_job(j, s, msg);
+      cv_done.notify_all();
+    } else {
+      j->state = JS::Resident;
+    }
+    cv.notify_all();
+  }
+}
+
+// Build and launch one packed round into a free slot; false if there is no
+// work or no free slot.
+bool ServerImpl::launch_round() {
+  Slot &S = slot[round & 1];
+  if (S.busy) {
+    if (hipEventQuery(S.ev_e) != hipSuccess) return false;
+    S.busy = false;
+  }
+  std::vector<SJob *> cand;
+  Prec P = Prec::F64;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (SJob *j : resident)
+      if (j->state == JS::Resident && j->next < j->ntr) {
+        if (cand.empty()) P = j->prec;
+        if (j->prec == P) cand.push_back(j);
+      }
+  }
+  if (cand.empty()) return false;
+
+  const int osz = out_bytes(P);
+  // column-block width minimising the padded lone-index work of the round
+  int nb = 5;
+  {
+    long best = -1;
+    for (int c = 8; c >= 4; --c) {
+      long cols = 0;
+      for (SJob *j : cand) {
+        const int vp = j->job->vp;
+        cols += (long)((vp + 16 * c - 1) / (16 * c)) * 16 * c * (long)vp * vp;
+      }
+      if (best < 0 || cols < best) { best = cols; nb = c; }
+    }
+  }
+  const int bm = wbuild_bm();
+  struct Pick { SJob *j; long t; };
+  std::vector<Pick> picks;
+  long tiles = 0, blks = 0;
+  size_t wbytes = 0;
+  auto tiles_of = [&](SJob *j) {
+    const long vp = j->job->vp;
+    return 3 * ((vp * vp + bm - 1) / bm) * ((vp + 16 * nb - 1) / (16 * nb));
+  };
+  auto fits = [&](SJob *j) {
+    const size_t vp = j->job->vp;
+    if ((int)picks.size() >= MAX_ITEMS) return false;
+    return tiles + tiles_of(j) <= MAX_TILES && blks + j->job->nsext <= MAX_BLKS &&
+           wbytes + 3 * vp * vp * vp * osz <= wcap;
+  };
+  auto take = [&](SJob *j) {
+    const size_t vp = j->job->vp;
+    picks.push_back({j, j->next});
+    tiles += tiles_of(j);
+    blks += j->job->nsext;
+    wbytes += 3 * vp * vp * vp * osz;
+    j->next++;
+  };
+  // fair share first, then fill in arrival order
+  const long share = std::max(1L, MAX_TILES / (long)cand.size());
+  for (SJob *j : cand) {
+    long got = 0;
+    while (j->next < j->ntr && got < share && fits(j)) { got += tiles_of(j); take(j); }
+  }
+  for (SJob *j : cand)
+    while (j->next < j->ntr && fits(j)) take(j);
+  if (picks.empty()) return false;
+
+  // items and maps in pinned memory
+  const int n = (int)picks.size();
+  long t0 = 0, b0 = 0;
+  size_t woff = 0;
+  for (int q = 0; q < n; ++q) {
+    SJob *j = picks[q].j;
+    Job &J = *j->job;
+    const Operands &op = J.op[(P == Prec::BF16X2) ? (int)Prec::BF16X3 : (int)P];
+    const long t = picks[q].t;
+    const int i = j->trip[3 * t], jj = j->trip[3 * t + 1], k = j->trip[3 * t + 2];
+    const size_t vp = J.vp, vp3 = vp * vp * vp;
+    const size_t es = (P == Prec::F64) ? 8 : (P == Prec::F32 ? 4 : 2);
+    void *W = S.W.as<char>() + woff;
+    woff += 3 * vp3 * osz;
+    WItem &w = S.h_wi[q];
+    w.Xs[0] = (const char *)op.X + (size_t)i * vp3 * es;
+    w.Xs[1] = (const char *)op.X + (size_t)jj * vp3 * es;
+    w.Xs[2] = (const char *)op.X + (size_t)k * vp3 * es;
+    w.T2 = op.T2; w.In = op.In;
+    w.xps = op.xps; w.tps = op.tps; w.ips = op.ips;
+    w.W = W; w.o = J.o; w.vp = (int)vp; w.i = i; w.j = jj; w.k = k;
+    w.mt = (int)((vp * vp + bm - 1) / bm);
+    w.nt = (int)((vp + 16 * nb - 1) / (16 * nb));
+    const long nt_ = 3L * w.mt * w.nt;
+    for (long x = 0; x < nt_; ++x) S.h_tmap[t0 + x] = q;
+    EItem &e = S.h_ei[q];
+    e.W = W; e.K = J.K.as<double>(); e.t1 = J.t1.as<double>();
+    e.eo = J.eo.as<double>(); e.ev = J.ev.as<double>(); e.sext = J.sext.as<int>();
+    e.part = S.part.as<double>() + b0;
+    e.o = J.o; e.v = J.v; e.vp = (int)vp; e.nT = (int)(vp / BOX);
+    e.i = i; e.j = jj; e.k = k; e.nsext = J.nsext;
+    for (long x = 0; x < J.nsext; ++x) S.h_bmap[b0 + x] = q;
+    RItem &r = S.h_ri[q];
+    r.part = e.part; r.out = j->eout.as<double>() + t; r.n = J.nsext;
+    r.w = 2.0 - (i == jj) - (jj == k);
+    t0 += nt_;
+    b0 += J.nsext;
+  }
+  for (int q = 0, acc = 0; q < n; ++q) {  // first tile / block of each item
+    S.h_tmap[t0 + q] = acc;
+    acc += (int)(3L * S.h_wi[q].mt * S.h_wi[q].nt);
+  }
+  for (int q = 0, acc = 0; q < n; ++q) {
+    S.h_bmap[b0 + q] = acc;
+    acc += S.h_ei[q].nsext;
+  }
+  HIPCHK(hipMemcpyAsync(S.witems.p, S.h_wi, n * sizeof(WItem), hipMemcpyHostToDevice, s_w));
+  HIPCHK(hipMemcpyAsync(S.tmap.p, S.h_tmap, (t0 + n) * sizeof(int), hipMemcpyHostToDevice, s_w));
+  HIPCHK(hipMemcpyAsync(S.eitems.p, S.h_ei, n * sizeof(EItem), hipMemcpyHostToDevice, s_w));
+  HIPCHK(hipMemcpyAsync(S.ritems.p, S.h_ri, n * sizeof(RItem), hipMemcpyHostToDevice, s_w));
+  HIPCHK(hipMemcpyAsync(S.bmap.p, S.h_bmap, (b0 + n) * sizeof(int), hipMemcpyHostToDevice, s_w));
+  HIPCHK(launch_wbuild(P, S.witems.as<WItem>(), S.tmap.as<int>(), n, 0, t0, nb, s_w));
+  HIPCHK(hipEventRecord(S.ev_w, s_w));
+  HIPCHK(hipStreamWaitEvent(s_e, S.ev_w, 0));
+  HIPCHK(launch_energy(P == Prec::F64, S.eitems.as<EItem>(), S.bmap.as<int>(), n, 0, b0, s_e));
+  HIPCHK(launch_reduce(S.ritems.as<RItem>(), n, s_e));
+  // jobs whose last triple is in this round: final fixed-order sum
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (SJob *j : cand) {
+      if (j->next == j->ntr && j->state == JS::Resident) {
+        HIPCHK(launch_sum(j->eout.as<double>(), j->ntr, j->esum.as<double>(), s_e));
+        HIPCHK(hipMemcpyAsync(j->h_E, j->esum.p, 8, hipMemcpyDeviceToHost, s_e));
+        HIPCHK(hipEventRecord(j->done_ev, s_e));
+        j->state = JS::Finishing;
+      }
+    }
+  }
+  HIPCHK(hipEventRecord(S.ev_e, s_e));
+  S.busy = true;
+  round++;
+  return true;
+}
+
+void ServerImpl::retire() {
+  std::vector<SJob *> fin;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (SJob *j : resident)
+      if (j->state == JS::Finishing && hipEventQuery(j->done_ev) == hipSuccess) fin.push_back(j);
+  }
+  for (SJob *j : fin) {
+    const double E = *j->h_E;
+    std::lock_guard<std::mutex> lk(mu);
+    j->E = E;
+    j->eout.release();
+    j->esum.release();
+    j->job.reset();
+    reserved -= j->footprint;
+    resident.remove(j);
+    retired++;
+    finish_job(j, TE_OK, "");
+    const double lat = std::chrono::duration<double>(j->t_done - j->t_submit).count();
+    const double svc = std::chrono::duration<double>(j->t_done - j->t_admit).count();
+    j->st.seconds = lat;
+    j->st.stage_seconds = std::chrono::duration<double>(j->t_staged - j->t_admit).count();
+    j->st.n_triples = j->ntr;
+    j->st.flops = (double)j->ntr * flops_per_triple(j->o, j->v);
+    j->st.tflops = j->st.flops / std::max(svc, 1e-12) / 1e12;
+  }
+  if (!fin.empty()) {
+    cv.notify_all();
+    cv_done.notify_all();
+  }
+}
+
+void ServerImpl::sched_loop() {
+  try {
+    HIPCHK(hipSetDevice(device));
+    for (;;) {
+      retire();
+      bool launched = launch_round();
+      std::unique_lock<std::mutex> lk(mu);
+      if (stop) break;
+      if (!launched) cv.wait_for(lk, std::chrono::microseconds(200));
+    }
+  } catch (const Fail &f) {
+    std::lock_guard<std::mutex> lk(mu);
+    fatal = f.msg;
+    for (auto &kv : jobs)
+      if (kv.second->state != JS::Done) finish_job(kv.second.get(), f.s, f.msg);
+    cv_done.notify_all();
+  }
+}
+
+void ServerImpl::start() {
+  HIPCHK(hipSetDevice(device));
+  HIPCHK(hipStreamCreateWithFlags(&s_w, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&s_e, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&s_stage, hipStreamNonBlocking));
+  wcap = std::min<size_t>((size_t)3 << 30, budget / 8);
+  for (Slot &S : slot) {
+    S.W.alloc(wcap, nullptr, 0);
+    S.part.alloc(MAX_BLKS * 8, nullptr, 0);
+    S.witems.alloc(MAX_ITEMS * sizeof(WItem), nullptr, 0);
+    S.eitems.alloc(MAX_ITEMS * sizeof(EItem), nullptr, 0);
+    S.ritems.alloc(MAX_ITEMS * sizeof(RItem), nullptr, 0);
+    S.tmap.alloc((MAX_TILES + MAX_ITEMS) * 4, nullptr, 0);
+    S.bmap.alloc((MAX_BLKS + MAX_ITEMS) * 4, nullptr, 0);
+    HIPCHK(hipHostMalloc((void **)&S.h_wi, MAX_ITEMS * sizeof(WItem), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&S.h_ei, MAX_ITEMS * sizeof(EItem), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&S.h_ri, MAX_ITEMS * sizeof(RItem), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&S.h_tmap, S.tmap.bytes, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&S.h_bmap, S.bmap.bytes, hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&S.ev_w, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&S.ev_e, hipEventDisableTiming));
+  }
+  const size_t scratch = 2 * (wcap + MAX_BLKS * 8 + (MAX_BLKS + MAX_ITEMS) * 4);
+  if (budget <= scratch + ((size_t)1 << 28))
+    throw Fail(TE_ENOMEM, "HBM budget too small for the server's round scratch");
+  arena.init(budget - scratch);
+  stager = std::thread([this] { stage_loop(); });
+  sched = std::thread([this] { sched_loop(); });
+}
+
+void ServerImpl::shutdown() {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    stop = true;
+  }
+  cv.notify_all();
+  if (stager.joinable()) stager.join();
+  if (sched.joinable()) sched.join();
+  (void)hipSetDevice(device);
+  if (s_w) (void)hipStreamSynchronize(s_w);
+  if (s_e) (void)hipStreamSynchronize(s_e);
+  if (s_stage) (void)hipStreamSynchronize(s_stage);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &kv : jobs) {
+      SJob *j = kv.second.get();
+      j->eout.release();
+      j->esum.release();
+      j->job.reset();
+      if (j->state != JS::Done) finish_job(j, TE_ECANCELED, "server destroyed");
+      if (j->done_ev) (void)hipEventDestroy(j->done_ev);
+      if (j->h_E) (void)hipHostFree(j->h_E);
+      j->done_ev = nullptr;
+      j->h_E = nullptr;
+    }
+  }
+  cv_done.notify_all();
+  for (Slot &S : slot) {
+    S.W.release(); S.part.release(); S.witems.release(); S.eitems.release();
+    S.ritems.release(); S.tmap.release(); S.bmap.release();
+    if (S.h_wi) (void)hipHostFree(S.h_wi);
+    if (S.h_ei) (void)hipHostFree(S.h_ei);
+    if (S.h_ri) (void)hipHostFree(S.h_ri);
+    if (S.h_tmap) (void)hipHostFree(S.h_tmap);
+    if (S.h_bmap) (void)hipHostFree(S.h_bmap);
+    if (S.ev_w) (void)hipEventDestroy(S.ev_w);
+    if (S.ev_e) (void)hipEventDestroy(S.ev_e);
+  }
+  arena.destroy();
+  if (s_w) (void)hipStreamDestroy(s_w);
+  if (s_e) (void)hipStreamDestroy(s_e);
+  if (s_stage) (void)hipStreamDestroy(s_stage);
+}
+
+}  // namespace te
 
 using namespace te;
 
+#define TE_GUARD_BEGIN try {
+#define TE_GUARD_END                                                                        \
+  }                                                                                         \
+  catch (const Fail &f) { return set_error(f.s, f.msg); }                                   \
+  catch (const std::bad_alloc &) { return set_error(TE_ENOMEM, "host allocation failed"); } \
+  catch (...) { return set_error(TE_EDEVICE, "unexpected exception"); }
+
 extern "C" {
-te_status te_server_create(const te_server_config *, te_server *) {
-  return set_error(TE_EINVAL, "serving is not available in this build");
+
+te_status te_server_create(const te_server_config *cfg_in, te_server *out) {
+  TE_GUARD_BEGIN
+  if (!out) return set_error(TE_EINVAL, "out is NULL");
+  te_server_config cfg{};
+  if (cfg_in) cfg = *cfg_in;
+  if (cfg.max_resident_jobs < 0 || cfg.max_queued_jobs < 0)
+    return set_error(TE_EINVAL, "negative limits");
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (cfg.device < 0 || cfg.device >= ndev) return set_error(TE_EINVAL, "bad device ordinal");
+  HIPCHK(hipSetDevice(cfg.device));
+  std::unique_ptr<ServerImpl> S(new ServerImpl());
+  S->device = cfg.device;
+  size_t freeb = 0, total = 0;
+  HIPCHK(hipMemGetInfo(&freeb, &total));
+  S->budget = cfg.hbm_budget ? cfg.hbm_budget : (size_t)(0.8 * (double)freeb);
+  if (S->budget > freeb) return set_error(TE_ENOMEM, "HBM budget exceeds free device memory");
+  S->max_resident = cfg.max_resident_jobs ? cfg.max_resident_jobs : 64;
+  S->max_queued = cfg.max_queued_jobs ? cfg.max_queued_jobs : 4096;
+  try {
+    S->start();
+  } catch (...) {
+    S->shutdown();
+    throw;
+  }
+  *out = reinterpret_cast<te_server>(S.release());
+  return TE_OK;
+  TE_GUARD_END
 }
-te_status te_submit(te_server, const te_problem *, te_precision, uint64_t *) {
-  return set_error(TE_EINVAL, "serving is not available in this build");
+
+te_status te_submit(te_server srv, const te_problem *prob, te_precision prec, uint64_t *ticket) {
+  TE_GUARD_BEGIN
+  if (!srv || !ticket) return set_error(TE_EINVAL, "server and ticket are required");
+  ServerImpl &S = *reinterpret_cast<ServerImpl *>(srv);
+  if (!prob) return set_error(TE_EINVAL, "problem is NULL");
+  if (prob->mem != TE_MEM_HOST) return set_error(TE_EINVAL, "te_submit takes host arrays");
+  if (prec < TE_FP64 || prec > TE_BF16X2) return set_error(TE_EINVAL, "bad precision");
+  if (prob->o < 1 || prob->v < 1 || prob->naux < 0)
+    return set_error(TE_EINVAL, "need o >= 1, v >= 1, naux >= 0");
+  if (!prob->eps_occ || !prob->eps_vir || !prob->t1 || !prob->t2)
+    return set_error(TE_EINVAL, "eps_occ, eps_vir, t1 and t2 are required");
+  if (prob->naux > 0 && (!prob->B_oo || !prob->B_ov || !prob->B_vv))
+    return set_error(TE_EINVAL, "naux > 0 needs B_oo, B_ov and B_vv");
+  if (prob->naux == 0 && (!prob->ovvv || !prob->ovoo || !prob->ovov))
+    return set_error(TE_EINVAL, "naux == 0 needs ovvv, ovoo and ovov");
+  if (pad_v(prob->v) / BOX > 1023) return set_error(TE_EINVAL, "v above 8184 is not supported");
+  const Prec P = static_cast<Prec>(prec);
+  const size_t fp = job_footprint(prob->o, prob->v, prob->naux, P);
+  const size_t vp = pad_v(prob->v);
+  if (fp > S.arena.cap || 3 * vp * vp * vp * (size_t)out_bytes(P) > S.wcap)
+    return set_error(TE_ENOMEM, "job footprint " + std::to_string(fp) +
+                                    " bytes can never fit the server budget");
+  {
+    const size_t bm = wbuild_bm(), nT = vp / BOX;
+    const size_t tiles = 3 * ((vp * vp + bm - 1) / bm) * ((vp + 63) / 64);
+    if (tiles > (size_t)MAX_TILES || nT * (nT + 1) * (nT + 2) / 6 > (size_t)MAX_BLKS)
+      return set_error(TE_ENOMEM, "one triple of this job exceeds a server round");
+  }
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.stop) return set_error(TE_EBUSY, "server is shutting down");
+    if (!S.fatal.empty()) return set_error(TE_EDEVICE, S.fatal);
+    if ((int)S.queue.size() >= S.max_queued) return set_error(TE_EBUSY, "queue is full");
+  }
+  std::unique_ptr<SJob> j(new SJob());
+  j->t_submit = clk::now();
+  j->prec = P;
+  j->o = prob->o; j->v = prob->v; j->naux = prob->naux;
+  j->footprint = fp;
+  j->hc.take(*prob);
+  j->trip = triple_list_host(prob->o);
+  j->ntr = (long)j->trip.size() / 3;
+  HIPCHK(hipSetDevice(S.device));
+  HIPCHK(hipHostMalloc((void **)&j->h_E, 8, hipHostMallocDefault));
+  HIPCHK(hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming));
+  std::lock_guard<std::mutex> lk(S.mu);
+  j->ticket = S.next_ticket++;
+  *ticket = j->ticket;
+  SJob *raw = j.get();
+  S.jobs.emplace(j->ticket, std::move(j));
+  if (raw->ntr == 0) {  // o = 1: only i=j=k, which contributes nothing
+    raw->E = 0.0;
+    S.finish_job(raw, TE_OK, "");
+    S.cv_done.notify_all();
+  } else {
+    S.queue.push_back(raw);
+    S.cv.notify_all();
+  }
+  return TE_OK;
+  TE_GUARD_END
 }
-te_status te_poll(te_server, uint64_t, double *, te_stats *) {
-  return set_error(TE_EINVAL, "serving is not available in this build");
+
+static te_status collect(ServerImpl &S, std::unique_lock<std::mutex> &lk, uint64_t ticket,
+                         double *e_t, te_stats *st, bool block) {
+  auto it = S.jobs.find(ticket);
+  if (it == S.jobs.end()) return set_error(TE_ENOTFOUND, "unknown ticket");
+  SJob *j = it->second.get();
+  if (block) S.cv_done.wait(lk, [&] { return j->state == JS::Done; });
+  if (j->state != JS::Done) return TE_PENDING;
+  te_status s = j->status;
+  if (s == TE_OK) {
+    if (e_t) *e_t = j->E;
+    if (st) *st = j->st;
+  } else {
+    set_error(s, j->err);
+  }
+  if (j->done_ev) (void)hipEventDestroy(j->done_ev);
+  if (j->h_E) (void)hipHostFree(j->h_E);
+  S.jobs.erase(it);
+  return s;
 }
-te_status te_wait(te_server, uint64_t, double *, te_stats *) {
-  return set_error(TE_EINVAL, "serving is not available in this build");
+
+te_status te_poll(te_server srv, uint64_t ticket, double *e_t, te_stats *st) {
+  TE_GUARD_BEGIN
+  if (!srv) return set_error(TE_EINVAL, "server is NULL");
+  ServerImpl &S = *reinterpret_cast<ServerImpl *>(srv);
+  std::unique_lock<std::mutex> lk(S.mu);
+  return collect(S, lk, ticket, e_t, st, false);
+  TE_GUARD_END
 }
-te_status te_server_destroy(te_server) {
-  return set_error(TE_EINVAL, "serving is not available in this build");
+
+te_status te_wait(te_server srv, uint64_t ticket, double *e_t, te_stats *st) {
+  TE_GUARD_BEGIN
+  if (!srv) return set_error(TE_EINVAL, "server is NULL");
+  ServerImpl &S = *reinterpret_cast<ServerImpl *>(srv);
+  std::unique_lock<std::mutex> lk(S.mu);
+  return collect(S, lk, ticket, e_t, st, true);
+  TE_GUARD_END
 }
+
+te_status te_server_destroy(te_server srv) {
+  TE_GUARD_BEGIN
+  if (!srv) return set_error(TE_EINVAL, "server is NULL");
+  ServerImpl *S = reinterpret_cast<ServerImpl *>(srv);
+  S->shutdown();
+  delete S;
+  return TE_OK;
+  TE_GUARD_END
 }
+
+}  // extern "C"

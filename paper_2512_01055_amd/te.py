@@ -43,7 +43,9 @@ class Config(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("seconds", C.c_double), ("flops", C.c_double), ("tflops", C.c_double),
                 ("n_triples", C.c_int64), ("stage_seconds", C.c_double),
-                ("assemble_flops", C.c_double)]
+                ("assemble_flops", C.c_double), ("w_kernel_seconds", C.c_double),
+                ("w_launches", C.c_int64), ("e_kernel_seconds", C.c_double),
+                ("e_launches", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -1,0 +1,125 @@
+"""Serving runtime on the device: packed mixed-job launches give each job the
+same result as a job run alone (bitwise, same precision), admission respects
+the HBM budget, and error paths report the documented statuses."""
+import threading
+
+import numpy as np
+import pytest
+
+from paper_2512_01055_amd.inputs import make_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _te():
+    from paper_2512_01055_amd import te
+    return te
+
+
+# mixed (o, v = 8 o, naux = 3 v) jobs as in the serving workload, small sizes
+MIX = [(8, 64, 192, 101), (5, 40, 120, 102), (10, 80, 240, 103), (8, 64, 192, 104),
+       (6, 48, 144, 105), (12, 96, 288, 106), (7, 56, 168, 107), (9, 72, 216, 108)]
+
+
+def _alone(te, P, prec):
+    with te.Job(P, device=0) as job:
+        return job.energy(prec)[0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_mix_equals_alone_bitwise(prec):
+    te = _te()
+    probs = [make_problem(*m) for m in MIX]
+    alone = [_alone(te, P, prec) for P in probs]
+    print(f"\n[serving mix of {len(probs)} jobs, {prec}]", flush=True)
+    with te.Server(device=0) as srv:
+        tickets = [srv.submit(P, prec) for P in probs]
+        got = [srv.wait(t) for t in tickets]
+    for (E, st), Ea, m in zip(got, alone, MIX):
+        assert E == Ea, (m, E, Ea)
+        assert st["n_triples"] == te.lib().te_num_triples(m[0])
+
+
+def test_mixed_precisions_in_one_server():
+    te = _te()
+    probs = [make_problem(*m) for m in MIX[:4]]
+    precs = ["fp64", "bf16x2", "fp32", "bf16x3"]
+    alone = [_alone(te, P, p) for P, p in zip(probs, precs)]
+    with te.Server(device=0) as srv:
+        tickets = [srv.submit(P, p) for P, p in zip(probs, precs)]
+        got = [srv.wait(t)[0] for t in tickets]
+    assert got == alone
+
+
+def test_admission_one_resident_job_at_a_time():
+    te = _te()
+    probs = [make_problem(8, 64, 192, 200 + q) for q in range(4)]
+    alone = [_alone(te, P, "fp64") for P in probs]
+    with te.Server(device=0, max_resident_jobs=1) as srv:
+        tickets = [srv.submit(P, "fp64") for P in probs]
+        got = [srv.wait(t)[0] for t in tickets]
+    assert got == alone
+
+
+# 512 MiB: round scratch takes a quarter plus ~100 MiB, the arena keeps
+# ~290 MiB, room for one o=12 v=104 job (~180 MiB) at a time
+TIGHT = 512 << 20
+
+
+def test_admission_under_tight_budget():
+    te = _te()
+    probs = [make_problem(12, 104, 312, 210 + q) for q in range(3)]
+    alone = [_alone(te, P, "fp64") for P in probs]
+    with te.Server(device=0, hbm_budget=TIGHT) as srv:
+        tickets = [srv.submit(P, "fp64") for P in probs]
+        got = [srv.wait(t)[0] for t in tickets]
+    assert got == alone
+
+
+def test_job_that_can_never_fit_is_enomem():
+    te = _te()
+    with te.Server(device=0, hbm_budget=TIGHT) as srv:
+        P = make_problem(24, 192, 576, 300)
+        with pytest.raises(te.TeError) as ei:
+            srv.submit(P, "fp64")
+        assert ei.value.status == te.ENOMEM
+
+
+def test_ticket_released_after_final_poll_and_concurrent_submit():
+    te = _te()
+    probs = [make_problem(*m) for m in MIX[:6]]
+    out = {}
+    with te.Server(device=0) as srv:
+        def client(q):
+            t = srv.submit(probs[q], "fp64")
+            out[q] = (t, srv.wait(t))
+        th = [threading.Thread(target=client, args=(q,)) for q in range(len(probs))]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        for q, (t, (E, st)) in out.items():
+            with pytest.raises(te.TeError) as ei:
+                srv.poll(t)
+            assert ei.value.status == te.ENOTFOUND
+        with pytest.raises(te.TeError) as ei:
+            srv.poll(12345678)
+        assert ei.value.status == te.ENOTFOUND
+    for q in range(len(probs)):
+        assert out[q][1][0] == _alone(te, probs[q], "fp64")
+
+
+def test_destroy_with_pending_jobs():
+    te = _te()
+    srv = te.Server(device=0)
+    for q in range(6):
+        srv.submit(make_problem(10, 80, 240, 400 + q), "fp64")
+    srv.close()            # must not hang or fault; pending jobs are dropped
+
+
+def test_o_equal_one_finishes_with_zero():
+    te = _te()
+    with te.Server(device=0) as srv:
+        t = srv.submit(make_problem(1, 16, 20, 500), "fp64")
+        E, st = srv.wait(t)
+    assert E == 0.0 and st["n_triples"] == 0
