@@ -50,6 +50,138 @@ def cpu_baseline(P, triples):
                       f"from the factors; {dt:.1f} s"}, {tuple(p[:3]): p[3] for p in parts}
 
 
+def bench_huge(args) -> int:
+    """o=100 v=800 naux=2400 with (vv|vo) assembled on the fly from the
+    factors: a fixed seeded subset of triples is timed and the full job is
+    extrapolated (per-triple time x N_t, plus the slice assemblies the
+    full-job schedule performs at the same cache size)."""
+    import torch
+    from paper_2512_01055_amd import te
+    from paper_2512_01055_amd.inputs import make_problem_device, sample_triples
+    o, v, naux, seed = 100, 800, 2400, 5
+    t0 = time.time()
+    P = make_problem_device(o, v, naux, seed)
+    log(f"inputs o={o} v={v} naux={naux} seed={seed} formed on the device in {time.time() - t0:.1f} s")
+    sample = sample_triples(o, args.sample, seed)
+    n = len(sample)
+    n_full = int(te.lib().te_num_triples(o))
+    fpt = te.flops_per_triple(o, v)
+    res = {}
+    for prec in args.precisions.split(","):
+        job = te.Job(P, device=0, x_mode="on_the_fly", x_cache_slices=args.cache)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        E, pt, st = job.energy_triples(sample, prec)
+        dt = time.perf_counter() - t1
+        job.free()
+        S = int(st["cache_slices"])
+        loads_full = int(te.lib().te_plan_slice_loads(o, S, 1))
+        t_asm = st["assemble_seconds"] / max(st["slices_assembled"], 1)
+        per_tr = max(dt - st["assemble_seconds"], 1e-9) / n
+        full = n_full * per_tr + loads_full * t_asm
+        res[prec] = {"subset_triples": n, "subset_seconds": round(dt, 3), "E_subset": E,
+                     "w_kernel_tflops": round(n * fpt / st["w_kernel_seconds"] / 1e12, 3),
+                     "subset_tflops_excl_assembly": round(n * fpt / (n * per_tr) / 1e12, 3),
+                     "slices_assembled_subset": int(st["slices_assembled"]),
+                     "assemble_seconds_subset": round(st["assemble_seconds"], 3),
+                     "seconds_per_slice": round(t_asm, 4), "cache_slices": S,
+                     "full_job_slice_loads": loads_full,
+                     "full_job_extrapolated_seconds": round(full, 1),
+                     "full_job_extrapolated_tflops": round(n_full * fpt / full / 1e12, 3)}
+        log(f"[{prec}] {json.dumps(res[prec])}")
+    if "fp64" in res:
+        for p_, r in res.items():
+            if p_ != "fp64":
+                r["dE_subset_vs_fp64"] = abs(r["E_subset"] - res["fp64"]["E_subset"])
+                r["dE_subset_rel"] = r["dE_subset_vs_fp64"] / abs(res["fp64"]["E_subset"])
+    head = res.get("fp64") or next(iter(res.values()))
+    print(json.dumps({"metric": "(T) o=100 v=800 naux=2400, (vv|vo) on the fly: extrapolated "
+                                "full-job TFLOP/s", "value": head["full_job_extrapolated_tflops"],
+                      "unit": "TFLOP/s", "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": f"(T) o={o} v={v} naux={naux} seed {seed}, "
+                                             f"{n} of {n_full} triples timed"},
+                      "precisions": res}), flush=True)
+    return 0
+
+
+def bench_serving(args) -> int:
+    """Mixed-size (T) jobs arriving as a Poisson process: the packed server
+    against sequential plain solves (te_init + te_energy + te_free, one job
+    at a time) on the same arrival trace. Reports jobs/s and p50/p99 latency
+    (arrival to result)."""
+    import threading
+    from paper_2512_01055_amd import te
+    from paper_2512_01055_amd.inputs import make_problem
+    rng = np.random.default_rng(4)
+    os_ = rng.integers(args.omin, args.omax + 1, size=args.jobs)
+    pool = {}
+    t0 = time.time()
+    for o in sorted(set(int(x) for x in os_)):
+        pool[o] = make_problem(o, 8 * o, 24 * o, 1000 + o)
+    log(f"serving: {args.jobs} jobs, o in [{args.omin},{args.omax}], pool of {len(pool)} problems "
+        f"drawn in {time.time() - t0:.1f} s")
+    work = sum(te.lib().te_num_triples(int(o)) * te.flops_per_triple(int(o), 8 * int(o)) for o in os_)
+
+    def run_seq(arrivals):
+        lat = []
+        t_start = time.perf_counter()
+        for o, a in zip(os_, arrivals):
+            now = time.perf_counter() - t_start
+            if now < a:
+                time.sleep(a - now)
+            with te.Job(pool[int(o)], device=0) as job:
+                job.energy(args.precision)
+            lat.append(time.perf_counter() - t_start - a)
+        return time.perf_counter() - t_start, lat
+
+    def run_srv(arrivals):
+        lat = [None] * len(os_)
+        with te.Server(device=0) as srv:
+            t_start = time.perf_counter()
+            tickets = []
+            for q, (o, a) in enumerate(zip(os_, arrivals)):
+                now = time.perf_counter() - t_start
+                if now < a:
+                    time.sleep(a - now)
+                tickets.append(srv.submit(pool[int(o)], args.precision))
+            for q, t in enumerate(tickets):
+                E, st = srv.wait(t)
+                lat[q] = st["seconds"]
+            span = time.perf_counter() - t_start
+        return span, lat
+
+    def summary(span, lat):
+        lat = np.sort(np.asarray(lat))
+        return {"jobs_per_s": round(len(lat) / span, 4), "makespan_s": round(span, 2),
+                "p50_s": round(float(np.percentile(lat, 50)), 3),
+                "p99_s": round(float(np.percentile(lat, 99)), 3)}
+
+    out = {}
+    sat = np.zeros(args.jobs)
+    log("serving: saturated arrivals, sequential")
+    span_seq, lat_seq = run_seq(sat)
+    out["saturated"] = {"sequential": summary(span_seq, lat_seq)}
+    log("serving: saturated arrivals, packed server")
+    span_p, lat_p = run_srv(sat)
+    out["saturated"]["packed"] = summary(span_p, lat_p)
+    cap = args.jobs / span_seq
+    rate = 0.8 * cap
+    arr = np.cumsum(rng.exponential(1.0 / rate, size=args.jobs))
+    log(f"serving: Poisson arrivals at {rate:.3f} jobs/s (0.8 x sequential capacity)")
+    span_seq2, lat_seq2 = run_seq(arr)
+    span_p2, lat_p2 = run_srv(arr)
+    out["poisson"] = {"rate_jobs_per_s": round(rate, 4),
+                      "sequential": summary(span_seq2, lat_seq2),
+                      "packed": summary(span_p2, lat_p2)}
+    print(json.dumps({"metric": "(T) serving mix: jobs/s and p50/p99 latency, packed vs sequential",
+                      "value": out["saturated"]["packed"]["jobs_per_s"], "unit": "jobs/s",
+                      "n_gpus": 1, "data": "synthetic", "precision": args.precision,
+                      "config": {"workload": f"{args.jobs} (T) jobs, o ~ U{{{args.omin}..{args.omax}}}, "
+                                             f"v = 8 o, naux = 3 v, seed 4; {work:.3e} flop in total"},
+                      "results": out}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,11 +196,22 @@ def main() -> int:
     ap.add_argument("--cpu-triples", type=int, default=2)
     ap.add_argument("--max-triples", type=int, default=0,
                     help="exploration only: evaluate the first N triples per step")
+    ap.add_argument("--workload", choices=("large", "huge", "serving"), default="large")
+    ap.add_argument("--sample", type=int, default=2000, help="huge: triples timed")
+    ap.add_argument("--cache", type=int, default=0, help="huge: slice cache size (0: auto)")
+    ap.add_argument("--jobs", type=int, default=256, help="serving: number of jobs")
+    ap.add_argument("--omin", type=int, default=8)
+    ap.add_argument("--omax", type=int, default=40)
+    ap.add_argument("--precision", default="fp64", help="serving: precision of every job")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by "
               "occupied triples across GPUs, which this build does not launch", file=sys.stderr)
         return 2
+    if args.workload == "huge":
+        return bench_huge(args)
+    if args.workload == "serving":
+        return bench_serving(args)
 
     import torch
     from paper_2512_01055_amd import te

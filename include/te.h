@@ -105,6 +105,11 @@ typedef struct te_stats {
   int64_t w_launches;
   double e_kernel_seconds;
   int64_t e_launches;
+  /* On-the-fly (vv|vo) mode: slices assembled, their device time, and the
+   * number of slices the cache held. */
+  int64_t slices_assembled;
+  double assemble_seconds;
+  int64_t cache_slices;
 } te_stats;
 
 typedef struct te_job_s *te_job;
@@ -140,6 +145,11 @@ int64_t te_num_triples(int32_t o);
 te_status te_triple_list(int32_t o, int32_t *ijk);
 /* Algorithmic flop count of one triple's W: 12 v^3 (v + o). */
 double te_flops_per_triple(int32_t o, int32_t v);
+/* On-the-fly mode planning: the number of (vv|vo) slice assemblies the
+ * schedule performs for the full triple list of o occupied orbitals with a
+ * cache of cache_slices (>= 3) slices and batches of up to `batch` triples.
+ * Returns -1 for invalid arguments. */
+int64_t te_plan_slice_loads(int32_t o, int32_t cache_slices, int32_t batch);
 
 /* ---------------------------------------------------------------------
  * Serving: jobs of mixed (o, v) arrive while others run. The server admits

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -370,12 +372,116 @@ static int batch_size(const Job &J, Prec p, long ntr) {
   return (int)std::max(1L, b);
 }
 
+// Execution plan for a list of triples: the order they run in, the batches,
+// and (on-the-fly mode) which (vv|vo) slice sits in which cache slot.
+struct Plan {
+  std::vector<long> order;                               // position -> caller index
+  std::vector<long> bfirst;                              // batch -> first position
+  std::vector<int> bcount;
+  std::vector<std::vector<std::pair<int, int>>> loads;   // batch -> (occupied p, slot)
+  std::vector<std::array<int, 3>> slot;                  // position -> slots of X_i, X_j, X_k
+  long nloads = 0;
+};
+
+static Plan plan_resident(long ntr, int B) {
+  Plan P;
+  P.order.resize(ntr);
+  for (long t = 0; t < ntr; ++t) P.order[t] = t;
+  for (long f = 0; f < ntr; f += B) {
+    P.bfirst.push_back(f);
+    P.bcount.push_back((int)std::min<long>(B, ntr - f));
+  }
+  P.loads.resize(P.bfirst.size());
+  return P;
+}
+
+// Occupied indices are grouped in blocks of S/3; triples run block-triple by
+// block-triple so that a cache of S slices is refilled about once per block
+// change. Within a batch every needed slice is resident; misses evict the
+// least recently used slice not needed by the batch.
+static Plan plan_on_the_fly(const int *ijk, long ntr, int B, int S) {
+  Plan P;
+  const int bs = std::max(1, S / 3);
+  P.order.resize(ntr);
+  for (long t = 0; t < ntr; ++t) P.order[t] = t;
+  std::stable_sort(P.order.begin(), P.order.end(), [&](long a, long b) {
+    const int *x = ijk + 3 * a, *y = ijk + 3 * b;
+    for (int d = 0; d < 3; ++d)
+      if (x[d] / bs != y[d] / bs) return x[d] / bs < y[d] / bs;
+    for (int d = 0; d < 3; ++d)
+      if (x[d] != y[d]) return x[d] < y[d];
+    return false;
+  });
+  std::vector<int> held(S, -1);        // slot -> occupied index
+  std::vector<long> last(S, -1);       // slot -> last batch that used it
+  std::map<int, int> where;            // occupied index -> slot
+  P.slot.resize(ntr);
+  long pos = 0, bno = 0;
+  while (pos < ntr) {
+    std::vector<int> need;
+    auto has = [&](int p) { return std::find(need.begin(), need.end(), p) != need.end(); };
+    long end = pos;
+    while (end < ntr && end - pos < B) {
+      const int *x = ijk + 3 * P.order[end];
+      std::vector<int> add;
+      for (int d = 0; d < 3; ++d)
+        if (!has(x[d]) && std::find(add.begin(), add.end(), x[d]) == add.end()) add.push_back(x[d]);
+      if ((int)(need.size() + add.size()) > S) break;
+      need.insert(need.end(), add.begin(), add.end());
+      ++end;
+    }
+    std::vector<std::pair<int, int>> loads;
+    for (int p : need) {
+      auto it = where.find(p);
+      if (it != where.end()) { last[it->second] = bno; continue; }
+      int victim = -1;
+      for (int q = 0; q < S; ++q) {
+        if (held[q] >= 0 && has(held[q])) continue;
+        if (victim < 0 || last[q] < last[victim]) victim = q;
+      }
+      if (held[victim] >= 0) where.erase(held[victim]);
+      held[victim] = p;
+      where[p] = victim;
+      last[victim] = bno;
+      loads.push_back({p, victim});
+    }
+    for (long q = pos; q < end; ++q) {
+      const int *x = ijk + 3 * P.order[q];
+      P.slot[q] = {where[x[0]], where[x[1]], where[x[2]]};
+    }
+    P.bfirst.push_back(pos);
+    P.bcount.push_back((int)(end - pos));
+    P.loads.push_back(loads);
+    P.nloads += (long)loads.size();
+    pos = end;
+    ++bno;
+  }
+  return P;
+}
+
+// Assemble X_p[x][y][f] = (px|yf) = sum_Q B^Q_px B^Q_yf (Eq. 6) into a cache
+// slot, in the precision the W build reads.
+static void assemble_slice(Job &J, Prec p, int occ, void *slot, double *tmp64, hipStream_t s) {
+  const int o = J.o, v = J.v, vp = J.vp, naux = J.naux;
+  const long vp2 = (long)vp * vp;
+  const size_t n = (size_t)vp2 * vp;
+  double *dst = p == Prec::F64 ? (double *)slot : tmp64;
+  HIPCHK(hipMemsetAsync(dst, 0, n * sizeof(double), s));
+  GemmTN g{J.Bov + (long)occ * v, J.Bvv, dst, v, v * v, naux, (long)o * v, (long)v * v,
+           v, vp2, vp2, v, vp, 1, 1.0};
+  HIPCHK(launch_gemm_tn(g, s));
+  if (p == Prec::F32) HIPCHK(launch_to_f32(tmp64, (float *)slot, n, s));
+  if (p == Prec::BF16X3 || p == Prec::BF16X2)
+    HIPCHK(launch_to_bf16_parts(tmp64, (uint16_t *)slot, n, 3, s));
+}
+
 void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double *per_triple,
                  te_stats *st) {
   auto t0 = std::chrono::steady_clock::now();
   const Operands &op = ensure_prec(J, p);
   auto t1 = std::chrono::steady_clock::now();
-  if (!op.X) throw Fail(TE_EINVAL, "(vv|vo) slices are not resident");
+  const bool fly = !J.x_resident;
+  if (!fly && !op.X) throw Fail(TE_EINVAL, "(vv|vo) slices are not resident");
 
   const int o = J.o, vp = J.vp;
   const int bm = wbuild_bm();
@@ -386,40 +492,65 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
   const int B = batch_size(J, p, ntr);
   const size_t vp3 = (size_t)vp * vp * vp;
   const size_t osz = out_size(p);
-  const long nbatch = (ntr + B - 1) / B;
+  const size_t es = elem_size(p);
 
   // scratch: W for two batches, partials for two batches, per-triple results
-  DBuf wbuf, part, eout, esum, witems, eitems, ritems;
+  DBuf wbuf, part, eout, esum, witems, eitems, ritems, cache, tmp64;
   wbuf.alloc(2 * (size_t)B * 3 * vp3 * osz, &J.used, J.budget);
   part.alloc(2 * (size_t)B * J.nsext * 8, &J.used, J.budget);
   eout.alloc((size_t)ntr * 8, &J.used, J.budget);
   esum.alloc(8, &J.used, J.budget);
 
+  Plan P;
+  size_t slot_bytes = 0;
+  if (fly) {
+    slot_bytes = vp3 * es * (size_t)nparts(p);
+    if (p != Prec::F64) tmp64.alloc(vp3 * 8, &J.used, J.budget);
+    long room = (long)((J.budget - std::min(J.budget, J.used + ((size_t)1 << 28))) / slot_bytes);
+    int S = J.x_cache ? J.x_cache : (int)std::min<long>(room, o);
+    S = std::min(S, o);
+    if (S < 3 || S > room)
+      throw Fail(TE_ENOMEM, "no room for three (vv|vo) slices of " + std::to_string(slot_bytes) +
+                                " bytes in the HBM budget");
+    cache.alloc((size_t)S * slot_bytes, &J.used, J.budget);
+    P = plan_on_the_fly(ijk, ntr, B, S);
+  } else {
+    P = plan_resident(ntr, B);
+  }
+  const long nbatch = (long)P.bfirst.size();
+
   std::vector<WItem> wi(ntr);
   std::vector<EItem> ei(ntr);
   std::vector<RItem> ri(ntr);
-  const size_t xs = vp3;  // slice stride in the resident layout
-  for (long t = 0; t < ntr; ++t) {
-    const int i = ijk[3 * t], j = ijk[3 * t + 1], k = ijk[3 * t + 2];
-    const long b = t / B, slot = b & 1, q = t - b * B;
-    void *W = wbuf.as<char>() + ((size_t)slot * B + q) * 3 * vp3 * osz;
-    const size_t es = elem_size(p);
-    WItem &w = wi[t];
-    w.Xs[0] = (const char *)op.X + (size_t)i * xs * es;
-    w.Xs[1] = (const char *)op.X + (size_t)j * xs * es;
-    w.Xs[2] = (const char *)op.X + (size_t)k * xs * es;
-    w.T2 = op.T2; w.In = op.In;
-    w.xps = op.xps; w.tps = op.tps; w.ips = op.ips;
-    w.W = W; w.o = o; w.vp = vp; w.i = i; w.j = j; w.k = k; w.mt = mt; w.nt = nt;
-    EItem &e = ei[t];
-    e.W = W; e.K = J.K.as<double>(); e.t1 = J.t1.as<double>();
-    e.eo = J.eo.as<double>(); e.ev = J.ev.as<double>(); e.sext = J.sext.as<int>();
-    e.part = part.as<double>() + ((size_t)slot * B + q) * J.nsext;
-    e.o = o; e.v = J.v; e.vp = vp; e.nT = vp / BOX; e.i = i; e.j = j; e.k = k;
-    e.nsext = J.nsext;
-    RItem &r = ri[t];
-    r.part = e.part; r.out = eout.as<double>() + t; r.n = J.nsext;
-    r.w = 2.0 - (i == j) - (j == k);
+  for (long b = 0; b < nbatch; ++b) {
+    for (int q = 0; q < P.bcount[b]; ++q) {
+      const long pos = P.bfirst[b] + q, t = P.order[pos];
+      const int i = ijk[3 * t], j = ijk[3 * t + 1], k = ijk[3 * t + 2];
+      const int sl = (int)(b & 1);
+      void *W = wbuf.as<char>() + ((size_t)sl * B + q) * 3 * vp3 * osz;
+      WItem &w = wi[pos];
+      if (fly) {
+        for (int d = 0; d < 3; ++d) w.Xs[d] = cache.as<char>() + (size_t)P.slot[pos][d] * slot_bytes;
+        w.xps = vp3;
+      } else {
+        w.Xs[0] = (const char *)op.X + (size_t)i * vp3 * es;
+        w.Xs[1] = (const char *)op.X + (size_t)j * vp3 * es;
+        w.Xs[2] = (const char *)op.X + (size_t)k * vp3 * es;
+        w.xps = op.xps;
+      }
+      w.T2 = op.T2; w.In = op.In;
+      w.tps = op.tps; w.ips = op.ips;
+      w.W = W; w.o = o; w.vp = vp; w.i = i; w.j = j; w.k = k; w.mt = mt; w.nt = nt;
+      EItem &e = ei[pos];
+      e.W = W; e.K = J.K.as<double>(); e.t1 = J.t1.as<double>();
+      e.eo = J.eo.as<double>(); e.ev = J.ev.as<double>(); e.sext = J.sext.as<int>();
+      e.part = part.as<double>() + ((size_t)sl * B + q) * J.nsext;
+      e.o = o; e.v = J.v; e.vp = vp; e.nT = vp / BOX; e.i = i; e.j = j; e.k = k;
+      e.nsext = J.nsext;
+      RItem &r = ri[pos];
+      r.part = e.part; r.out = eout.as<double>() + t; r.n = J.nsext;
+      r.w = 2.0 - (i == j) - (j == k);
+    }
   }
   witems.alloc(ntr * sizeof(WItem), &J.used, J.budget);
   eitems.alloc(ntr * sizeof(EItem), &J.used, J.budget);
@@ -432,12 +563,19 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
 
   const bool f64 = p == Prec::F64;
   // timing events around every launch (device time of each kernel)
-  TimingEvents tw(nbatch), te_(nbatch);
+  TimingEvents tw(nbatch), te_(nbatch), ta(fly ? nbatch : 0);
   for (long b = 0; b < nbatch; ++b) {
     const int slot = (int)(b & 1);
-    const long first = b * B;
-    const int cnt = (int)std::min<long>(B, ntr - first);
+    const long first = P.bfirst[b];
+    const int cnt = P.bcount[b];
     if (b >= 2) HIPCHK(hipStreamWaitEvent(J.s_aux, J.ev_e[slot], 0));
+    // slices this batch needs: assembled on the W stream, after every earlier
+    // W build (which may still read the slot being refilled)
+    if (fly) HIPCHK(hipEventRecord(ta.start[b], J.s_aux));
+    for (auto &ld : P.loads[b])
+      assemble_slice(J, p, ld.first, cache.as<char>() + (size_t)ld.second * slot_bytes,
+                     tmp64.as<double>(), J.s_aux);
+    if (fly) HIPCHK(hipEventRecord(ta.stop[b], J.s_aux));
     HIPCHK(hipEventRecord(tw.start[b], J.s_aux));
     HIPCHK(launch_wbuild(p, witems.as<WItem>() + first, nullptr, cnt, tiles, (long)cnt * tiles,
                          nbk, J.s_aux));
@@ -465,12 +603,21 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
     st->n_triples = ntr;
     st->flops = (double)ntr * flops_per_triple(o, J.v);
     st->tflops = st->flops / std::max(st->seconds, 1e-12) / 1e12;
-    st->assemble_flops = 0.0;
+    st->assemble_flops = (double)P.nloads * 2.0 * J.naux * (double)J.v * J.v * J.v;
     st->w_kernel_seconds = tw.total();
     st->w_launches = nbatch;
     st->e_kernel_seconds = te_.total();
     st->e_launches = nbatch;
+    st->slices_assembled = P.nloads;
+    st->assemble_seconds = fly ? ta.total() : 0.0;
+    st->cache_slices = fly ? (int64_t)(cache.bytes / std::max<size_t>(slot_bytes, 1)) : 0;
   }
+}
+
+int64_t plan_slice_loads(int o, int S, int B) {
+  std::vector<int> t = triple_list_host(o);
+  Plan P = plan_on_the_fly(t.data(), (long)t.size() / 3, B, S);
+  return P.nloads;
 }
 
 Job::~Job() {
@@ -585,12 +732,11 @@ Job *make_job(const te_problem *P, const te_config *cfg_in, const JobOpts *opts)
   } else if (cfg.x_mode == TE_X_RESIDENT) {
     J->x_resident = true;
   } else if (cfg.x_mode == TE_X_ON_THE_FLY) {
-    throw Fail(TE_EINVAL, "on-the-fly slice assembly is not available in this build");
+    J->x_resident = false;
   } else {
     J->x_resident = xbytes <= J->budget / 2;
-    if (!J->x_resident)
-      throw Fail(TE_ENOMEM, "(vv|vo) does not fit the budget and on-the-fly assembly is off");
   }
+  J->x_cache = std::max(0, cfg.x_cache_slices);
 
   // sextets of 8^3 boxes
   J->nT = (int)(vp / BOX);
@@ -707,6 +853,15 @@ te_status te_triple_list(int32_t o, int32_t *ijk) {
 }
 
 double te_flops_per_triple(int32_t o, int32_t v) { return flops_per_triple(o, v); }
+
+int64_t te_plan_slice_loads(int32_t o, int32_t cache_slices, int32_t batch) {
+  if (o < 1 || cache_slices < 3 || batch < 1) return -1;
+  try {
+    return plan_slice_loads(o, cache_slices, batch);
+  } catch (...) {
+    return -1;
+  }
+}
 
 const char *te_strerror(te_status s) {
   switch (s) {

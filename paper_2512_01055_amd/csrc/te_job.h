@@ -73,6 +73,7 @@ struct Job {
   hipEvent_t ev_w[2] = {nullptr, nullptr}, ev_e[2] = {nullptr, nullptr}, ev_start = nullptr;
   size_t budget = 0, used = 0;
   bool x_resident = true;
+  int x_cache = 0;             // on-the-fly mode: slices cached (0: automatic)
   Arena *arena = nullptr;      // server jobs allocate from the server's arena
   bool own_aux = true;         // false: no second stream / events (server jobs)
 
@@ -104,5 +105,6 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
 std::vector<int> triple_list_host(int o);
 std::vector<int> sextet_list(int nT);
 double flops_per_triple(int o, int v);
+int64_t plan_slice_loads(int o, int S, int B);
 
 }  // namespace te

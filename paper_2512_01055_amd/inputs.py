@@ -119,3 +119,72 @@ def sample_triples(o: int, n: int, seed: int) -> np.ndarray:
             idx.pop()
             idx.add(int(pool[rng.integers(len(pool))]))
     return allt[sorted(idx)]
+
+
+def draw_factors(o: int, v: int, naux: int, seed: int, *, b_std: float = 0.05,
+                 t1_std: float = 1e-3):
+    """The random draws of make_problem (same stream, same values) without
+    forming the doubles: returns (eps_occ, eps_vir, t1, B_oo, B_ov, B_vv)."""
+    rng = np.random.default_rng(seed)
+    eps_occ = rng.uniform(-1.5, -0.3, o)
+    eps_vir = rng.uniform(0.1, 3.0, v)
+    B_oo = _sym_normal(rng, naux, o, b_std)
+    B_ov = rng.standard_normal((naux, o, v)) * b_std
+    B_vv = _sym_normal(rng, naux, v, b_std)
+    t1 = rng.standard_normal((o, v)) * t1_std
+    return eps_occ, eps_vir, t1, B_oo, B_ov, B_vv
+
+
+class LazyDoubles:
+    """Host view of t2 = (ia|jb)/(e_i+e_j-e_a-e_b) that forms only what is
+    indexed: t2[i, j] -> [v][v] and t2[:, j] -> [o][v][v]. Same definition as
+    mp2_doubles, for problems whose full t2 does not fit host memory."""
+
+    def __init__(self, eps_occ, eps_vir, B_ov):
+        self.eo, self.ev, self.B = eps_occ, eps_vir, B_ov
+        naux, o, v = B_ov.shape
+        self.shape = (o, o, v, v)
+
+    def _pair(self, i, j):
+        X = self.B[:, i, :].T @ self.B[:, j, :]          # (ia|jb)
+        Y = self.B[:, j, :].T @ self.B[:, i, :]          # (jb|ia)
+        M = 0.5 * (X + Y.T)
+        den = (self.eo[i] + self.eo[j]) - (self.ev[:, None] + self.ev[None, :])
+        return M / den
+
+    def __getitem__(self, key):
+        i, j = key
+        if isinstance(i, slice):
+            return np.stack([self._pair(q, j) for q in range(self.shape[0])[i]])
+        return self._pair(i, j)
+
+
+def make_problem_device(o: int, v: int, naux: int, seed: int, device="cuda:0", *,
+                        b_std: float = 0.05, t1_std: float = 1e-3):
+    """make_problem with the doubles formed on the device (torch, FP64), for
+    sizes whose o^2 v^2 array is too large to build on the host. The draws
+    are identical to make_problem's; t2 differs from the host version only by
+    the rounding order of its (ia|jb) sums. Returns an object with torch
+    device tensors eps_occ, eps_vir, t1, t2, B_oo, B_ov, B_vv and o, v, naux."""
+    import torch
+    eo, ev, t1, B_oo, B_ov, B_vv = draw_factors(o, v, naux, seed, b_std=b_std, t1_std=t1_std)
+    dev = torch.device(device)
+    out = type("DeviceProblem", (), {})()
+    out.o, out.v, out.naux, out.seed = o, v, naux, seed
+    for name, x in (("eps_occ", eo), ("eps_vir", ev), ("t1", t1), ("B_oo", B_oo),
+                    ("B_ov", B_ov), ("B_vv", B_vv)):
+        setattr(out, name, torch.from_numpy(x).to(dev))
+    del B_vv
+    L = out.B_ov.reshape(naux, o * v)
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=dev)
+    for i in range(o):                                  # (ia|jb) for all j, row block i
+        t2[i] = (L[:, i * v:(i + 1) * v].T @ L).reshape(v, o, v).permute(1, 0, 2)
+    t2 += t2.permute(1, 0, 3, 2).clone()
+    t2 *= 0.5
+    e_o, e_v = out.eps_occ, out.eps_vir
+    for i in range(o):
+        den = (e_o[i] + e_o)[:, None, None] - (e_v[:, None] + e_v[None, :])[None]
+        t2[i] /= den
+    out.t2 = t2
+    torch.cuda.synchronize()
+    return out

@@ -45,7 +45,8 @@ class Stats(C.Structure):
                 ("n_triples", C.c_int64), ("stage_seconds", C.c_double),
                 ("assemble_flops", C.c_double), ("w_kernel_seconds", C.c_double),
                 ("w_launches", C.c_int64), ("e_kernel_seconds", C.c_double),
-                ("e_launches", C.c_int64)]
+                ("e_launches", C.c_int64), ("slices_assembled", C.c_int64),
+                ("assemble_seconds", C.c_double), ("cache_slices", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -59,7 +60,7 @@ class ServerConfig(C.Structure):
 _lib: Optional[C.CDLL] = None
 
 EXPORTS = ["te_init", "te_energy", "te_energy_triples", "te_free", "te_num_triples",
-           "te_triple_list", "te_flops_per_triple", "te_server_create", "te_submit",
+           "te_triple_list", "te_flops_per_triple", "te_plan_slice_loads", "te_server_create", "te_submit",
            "te_poll", "te_wait", "te_server_destroy", "te_strerror", "te_last_error"]
 
 
@@ -90,6 +91,8 @@ def lib() -> C.CDLL:
     L.te_triple_list.argtypes = [C.c_int32, C.c_void_p]
     L.te_flops_per_triple.argtypes = [C.c_int32, C.c_int32]
     L.te_flops_per_triple.restype = C.c_double
+    L.te_plan_slice_loads.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+    L.te_plan_slice_loads.restype = C.c_int64
     L.te_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(P)]
     L.te_submit.argtypes = [P, C.POINTER(Problem), S, C.POINTER(C.c_uint64)]
     L.te_poll.argtypes = [P, C.c_uint64, C.POINTER(C.c_double), C.POINTER(Stats)]

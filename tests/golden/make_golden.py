@@ -5,6 +5,8 @@ from the device library.
 
     python tests/golden/make_golden.py medium     # all 1520 triples, o=20 v=200
     python tests/golden/make_golden.py large      # sampled triples, o=40 v=400
+    python tests/golden/make_golden.py huge [dir] # sampled triples, o=100 v=800
+                                                  # (t2 formed lazily; ~50 GB RAM)
 """
 import json
 import os
@@ -15,9 +17,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
-from paper_2512_01055_amd.inputs import LARGE, MEDIUM, make_problem  # noqa: E402
+from paper_2512_01055_amd.inputs import (HUGE, LARGE, MEDIUM, LazyDoubles,  # noqa: E402
+                                         draw_factors, make_problem)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+HUGE_TRIPLES = [(0, 0, 1), (3, 50, 99), (98, 99, 99)]
 
 # triples of the large workload checked one by one: both i=j<k and i<j=k
 # kinds, first and last occupied orbitals, a generic triple
@@ -45,7 +49,27 @@ def run(name, shape, b_std, triples=None):
     print(f"{path}: E = {E:.16e} over {len(parts)} triples in {out['oracle_seconds']:.1f} s")
 
 
+def run_huge(outdir):
+    o, v, naux, seed = HUGE
+    eo, ev, t1, B_oo, B_ov, B_vv = draw_factors(o, v, naux, seed)
+    t2 = LazyDoubles(eo, ev, B_ov)
+    ints = oracle.DFIntegrals(B_oo, B_ov, B_vv, max_cached=3)
+    t0 = time.time()
+    E, parts = oracle.energy(eo, ev, t1, t2, ints, triple_subset=HUGE_TRIPLES)
+    out = {"generator": "paper_2512_01055_amd.inputs.draw_factors + LazyDoubles",
+           "o": o, "v": v, "naux": naux, "seed": seed, "b_std": 0.05, "complete": False,
+           "E": E, "triples": [[int(p[0]), int(p[1]), int(p[2])] for p in parts],
+           "e": [p[3] for p in parts], "oracle_seconds": time.time() - t0}
+    path = os.path.join(outdir, "huge_o100_v800_seed5_sample.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=0)
+    print(f"{path}: {len(parts)} triples in {out['oracle_seconds']:.1f} s")
+
+
 if __name__ == "__main__":
+    if sys.argv[1:2] == ["huge"]:
+        run_huge(sys.argv[2] if len(sys.argv) > 2 else HERE)
+        sys.exit(0)
     which = sys.argv[1:] or ["medium", "large"]
     if "medium" in which:
         run("medium_o20_v200_seed2", MEDIUM, 0.05)

@@ -210,3 +210,55 @@ def test_budget_too_small_is_enomem():
     with pytest.raises(te.TeError) as ei:
         te.Job(P, device=0, hbm_budget=1 << 20)
     assert ei.value.status == te.ENOMEM
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("slices", [3, 4, 7])
+def test_on_the_fly_slices_equal_resident(prec, slices):
+    """(vv|vo) assembled from the factors into a small slice cache (many
+    evictions) gives every triple bitwise the value of the resident layout."""
+    te = _te()
+    P = make_problem(9, 48, 40, 28)
+    with te.Job(P, device=0, x_mode="resident") as job:
+        E_r, _, pt_r = job.energy(prec, per_triple=True)
+    with te.Job(P, device=0, x_mode="on_the_fly", x_cache_slices=slices) as job:
+        E_f, st, pt_f = job.energy(prec, per_triple=True)
+        sub = sample_triples(P.o, 12, 5)
+        _, ps, _ = job.energy_triples(sub, prec)
+    assert np.array_equal(pt_f, pt_r) and E_f == E_r
+    allt = te.triple_list(P.o)
+    idx = [int(np.nonzero((allt == s).all(1))[0][0]) for s in sub]
+    assert np.array_equal(ps, pt_r[idx])
+    assert st["assemble_flops"] > 0
+
+
+def test_on_the_fly_matches_oracle():
+    P = make_problem(6, 30, 90, 1)
+    E_ref, e_ref, _ = oracle_parts("small", P)
+    te = _te()
+    with te.Job(P, device=0, x_mode="on_the_fly", x_cache_slices=3) as job:
+        E, _, pt = job.energy("fp64", per_triple=True)
+    assert abs(E - E_ref) <= 1e-11 * abs(E_ref)
+    assert np.all(np.abs(pt - e_ref) <= 1e-11 * np.abs(e_ref))
+
+
+def test_huge_sampled_triples_on_the_fly():
+    """o=100 v=800 naux=2400 with (vv|vo) assembled on the fly, in the mode
+    the benchmark times; triples checked against stored oracle values."""
+    path = os.path.join(GOLDEN, "huge_o100_v800_seed5_sample.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle values for o=100 v=800 are missing")
+    g = json.load(open(path))
+    from paper_2512_01055_amd.inputs import HUGE, make_problem_device
+    te = _te()
+    print("\n[huge o=100 v=800: forming inputs on the device]", flush=True)
+    P = make_problem_device(*HUGE)
+    e_ref = np.array(g["e"])
+    with te.Job(P, device=0, x_mode="on_the_fly") as job:
+        for prec in ("fp64", "bf16x3"):
+            print(f"[huge prec={prec}]", flush=True)
+            _, pt, st = job.energy_triples(g["triples"], prec)
+            rel = np.abs(pt - e_ref) / np.abs(e_ref)
+            print(f"per-triple rel max {rel.max():.3e}, cache {st['cache_slices']} slices")
+            assert np.all(rel <= (1e-11 if prec == "fp64" else TOL[prec]))
+    del P
