@@ -203,6 +203,9 @@ def main() -> int:
     ap.add_argument("--omin", type=int, default=8)
     ap.add_argument("--omax", type=int, default=40)
     ap.add_argument("--precision", default="fp64", help="serving: precision of every job")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (a known-size copy "
+                         "kernel for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by "
@@ -216,6 +219,14 @@ def main() -> int:
     import torch
     from paper_2512_01055_amd import te
     from paper_2512_01055_amd.inputs import make_problem
+
+    if args.calib_copy_mib:
+        x = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read, {args.calib_copy_mib} MiB written")
+        del x, y
 
     o, v, naux, seed = args.o, args.v, args.naux, args.seed
     t0 = time.time()

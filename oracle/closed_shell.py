@@ -172,16 +172,21 @@ def triple_weight(i: int, j: int, k: int) -> float:
 
 
 def triple_energy(i: int, j: int, k: int, eps_occ, eps_vir, t1, t2, ints,
-                  split: bool = False):
+                  split: bool = False, progress=None):
     """e_ijk = w_ijk * sum_abc (W + V) Z / D for one occupied triple i<=j<=k.
 
     With split=True returns (e4, e5): the part from W alone and the part
-    from V (E = e4 + e5).
+    from V (E = e4 + e5). progress, if given, is called with a short string
+    after each stage (long runs report that they are alive).
     """
     W = w_tensor(i, j, k, ints, t2)
+    if progress:
+        progress(f"W of {(i, j, k)} formed")
     Vt = v_tensor(i, j, k, ints, t1)
     D = d_tensor(i, j, k, eps_occ, eps_vir)
     Z = z_tensor(W)
+    if progress:
+        progress(f"V, D, Z of {(i, j, k)} formed")
     w = triple_weight(i, j, k)
     if split:
         return w * _fsum((W * Z / D).ravel()), w * _fsum((Vt * Z / D).ravel())

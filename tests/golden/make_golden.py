@@ -55,7 +55,18 @@ def run_huge(outdir):
     t2 = LazyDoubles(eo, ev, B_ov)
     ints = oracle.DFIntegrals(B_oo, B_ov, B_vv, max_cached=3)
     t0 = time.time()
-    E, parts = oracle.energy(eo, ev, t1, t2, ints, triple_subset=HUGE_TRIPLES)
+    parts = []
+
+    def say(msg):
+        print(f"{msg} ({time.time() - t0:.0f} s)", flush=True)
+    for (i, j, k) in HUGE_TRIPLES:             # one at a time, reporting progress
+        for p in sorted({i, j, k}):
+            ints.ovvv(p)
+            say(f"slice {p} assembled")
+        e = oracle.triple_energy(i, j, k, eo, ev, t1, t2, ints, progress=say)
+        parts.append((i, j, k, e))
+        say(f"triple {(i, j, k)}: e = {e:.16e}")
+    E = sum(p[3] for p in parts)
     out = {"generator": "paper_2512_01055_amd.inputs.draw_factors + LazyDoubles",
            "o": o, "v": v, "naux": naux, "seed": seed, "b_std": 0.05, "complete": False,
            "E": E, "triples": [[int(p[0]), int(p[1]), int(p[2])] for p in parts],
