@@ -31,6 +31,24 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source has changed since the counters were taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2512_01055_amd", "csrc", "te_kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(path):
+            if line.startswith("traffic_bytes_per_launch:"):
+                f = line.split()
+                d = dict(zip(f[0::2], f[1::2]))
+                if (d.get("kernel:") == kernel and d.get("workload:") == workload
+                        and d.get("source_sha256_16:") == h):
+                    return float(d["traffic_bytes_per_launch:"])
+    return None
+
+
 def cpu_baseline(P, triples):
     """The CPU oracle as it stands, on a bounded sample of the same workload."""
     import oracle
@@ -299,7 +317,9 @@ def main() -> int:
                    "precision": head},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
                      "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_TFLOPS[head], 4), "traffic": None,
+                     "frac": round(achieved / PEAK_TFLOPS[head], 4),
+                     "traffic": measured_traffic(f"wbuild_kernel<{head}>", f"o{o}_v{v}"),
+                     "traffic_unit": "bytes/launch",
                      "kernel": f"wbuild_kernel<{head}>",
                      "avg_launch_ms": round(r["w_kernel_avg_ms"], 4)},
     }
