@@ -46,18 +46,29 @@ template <> struct Tr<Prec::BF16X2> {
   static constexpr int KT = 32, PAD = 8, NP = 2, KM = 32, ROWQ = 4;
 };
 
+// Global-address-space views. Operand pointers reach the kernels through
+// item structs in memory, so the compiler sees generic pointers and would
+// emit FLAT accesses; FLAT loads count against the LDS counter too, which
+// makes every wait for LDS fragments also wait for the next tile's prefetch.
+template <typename T> using gptr = const __attribute__((address_space(1))) T *;
+template <typename T> using gptr_w = __attribute__((address_space(1))) T *;
+template <typename T> __device__ inline T gld(const T *p) { return *(gptr<T>)(p); }
+template <typename T> __device__ inline void gst(T *p, T x) { *(gptr_w<T>)(p) = x; }
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // Eight consecutive elements, moved as 16-byte words.
 template <typename T> struct Chunk {
   static constexpr int NQ = sizeof(T) * 8 / 16;
-  uint4 q[NQ];
+  u32x4 q[NQ];
   __device__ T get(int e) const { return reinterpret_cast<const T *>(q)[e]; }
   __device__ void set(int e, T x) { reinterpret_cast<T *>(q)[e] = x; }
   __device__ void zero() {
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) q[i] = make_uint4(0, 0, 0, 0);
+    for (int i = 0; i < NQ; ++i) q[i] = u32x4{0u, 0u, 0u, 0u};
   }
   __device__ void load(const T *p) {
-    const uint4 *s = reinterpret_cast<const uint4 *>(p);
+    gptr<u32x4> s = (gptr<u32x4>)(p);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) q[i] = s[i];
   }
@@ -282,7 +293,7 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
           int seg = kg >= o;
           long off = rowI[u][seg] + (kg - seg * o);
 #pragma unroll
-          for (int p = 0; p < NP; ++p) rb[u][p].set(e, ok ? In[p * w.ips + off] : T(0));
+          for (int p = 0; p < NP; ++p) rb[u][p].set(e, ok ? gld(In + p * w.ips + off) : T(0));
         }
       }
     }
@@ -415,7 +426,7 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
           if (g == 0) { a = p0; b = p1; c = n; }
           else if (g == 1) { a = n; b = p0; c = p1; }
           else { a = p0; b = n; c = p1; }
-          Wg[box_off(a, b, c, nT)] = (Out)acc[rb_][cb][r];
+          gst(Wg + box_off(a, b, c, nT), (Out)acc[rb_][cb][r]);
         }
       }
 }
@@ -480,7 +491,7 @@ __global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ it
     if (canon[s] != s) continue;
     int r = idx & (BOX3 - 1);
     long base = ((((long)bx[s][0] * nT + bx[s][1]) * nT + bx[s][2]) << 9) + r;
-    double wv = ((double)W0[base] + (double)W1[base]) + (double)W2[base];
+    double wv = ((double)gld(W0 + base) + (double)gld(W1 + base)) + (double)gld(W2 + base);
     box[s * BX_S + bxi(r >> 6, (r >> 3) & 7, r & 7)] = wv;
   }
   __syncthreads();
@@ -505,10 +516,10 @@ __global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ it
                          - 2.0 * box[sd + bxi(x0, x2, x1)] - 2.0 * box[se + bxi(x1, x0, x2)]
                          - 2.0 * box[sf + bxi(x2, x1, x0)];
         // singles term (Eq. 3): t_i^a (jb|kc) + t_j^b (ia|kc) + t_k^c (ia|jb)
-        const double vt = t1i[a] * e.K[(((long)j * vp + b) * o + k) * vp + c]
-                        + t1j[b] * e.K[(((long)i * vp + a) * o + k) * vp + c]
-                        + t1k[c] * e.K[(((long)i * vp + a) * o + j) * vp + b];
-        const double d = ((eijk - e.ev[a]) - e.ev[b]) - e.ev[c];
+        const double vt = gld(t1i + a) * gld(e.K + (((long)j * vp + b) * o + k) * vp + c)
+                        + gld(t1j + b) * gld(e.K + (((long)i * vp + a) * o + k) * vp + c)
+                        + gld(t1k + c) * gld(e.K + (((long)i * vp + a) * o + j) * vp + b);
+        const double d = ((eijk - gld(e.ev + a)) - gld(e.ev + b)) - gld(e.ev + c);
         acc += (w0 + vt) * z / d;
       }
     }
