@@ -4,8 +4,10 @@ One step is one whole (T) job on the synthetic o=40, v=400, naux=1200
 workload with the inputs already in HBM: staging from the factors
 (integral assembly, padded layouts, precision copies), the W build over every
 occupied triple, the fused V/D/energy consumer and the reductions, ending
-with E(T) on the host. FP64 is the headline; FP32 and the split-BF16 modes
-run the same step and report |dE(T)| against the FP64 result.
+with E(T) on the host. FP64 is the headline and runs the whole job. FP32 and
+the split-BF16 modes run the same step over a fixed leading slice of the
+triple list (--secondary-frac, default 10%) and report |dE(T)| against the
+FP64 partials of the same triples.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precisions fp64,fp32,...]
 """
@@ -211,6 +213,8 @@ def main() -> int:
     ap.add_argument("--naux", type=int, default=1200)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--secondary-frac", type=float, default=0.1,
+                    help="fraction of the triple list (leading slice) the non-FP64 precisions time")
     ap.add_argument("--cpu-triples", type=int, default=2)
     ap.add_argument("--max-triples", type=int, default=0,
                     help="exploration only: evaluate the first N triples per step")
@@ -266,14 +270,29 @@ def main() -> int:
     stream = torch.cuda.current_stream()
 
     results = {}
-    for prec in args.precisions.split(","):
+    precs = args.precisions.split(",")
+    head = "fp64" if "fp64" in precs else precs[0]
+    # secondary precisions time a fixed leading slice of the triple list
+    n_sec = n_tr if args.secondary_frac >= 1.0 else max(1, int(round(n_tr * args.secondary_frac)))
+    sec_subset = (subset if subset is not None else te.triple_list(o))[:n_sec]
+    head_pt = None
+    for prec in precs:
+        is_head = prec == head
+        n_this = n_tr if is_head else n_sec
+        fl_this = n_this * te.flops_per_triple(o, v)
+
         def step():
+            nonlocal head_pt
             job = te.Job(D, device=0, stream=stream)
-            if subset is None:
-                E, st = job.energy(prec)
+            if is_head and subset is None:
+                E, st, pt = job.energy(prec, per_triple=True)
+            elif is_head:
+                E, pt, st = job.energy_triples(subset, prec)
             else:
-                E, _, st = job.energy_triples(subset, prec)
+                E, pt, st = job.energy_triples(sec_subset, prec)
             job.free()
+            if is_head:
+                head_pt = pt
             return E, st
         for w in range(args.warmup):
             log(f"[{prec}] warmup {w + 1}/{args.warmup}")
@@ -293,15 +312,14 @@ def main() -> int:
         wsec = sum(s_["w_kernel_seconds"] for s_ in sts)
         wl = sum(s_["w_launches"] for s_ in sts)
         results[prec] = {
-            "E": E, "seconds": dt, "ms_per_step": dt / args.steps * 1e3,
-            "tflops": fl_job * args.steps / dt / 1e12,
+            "E": E, "triples": n_this, "seconds": dt, "ms_per_step": dt / args.steps * 1e3,
+            "tflops": fl_this * args.steps / dt / 1e12,
             "w_kernel_avg_ms": wsec / max(wl, 1) * 1e3,
-            "w_flops_per_launch": fl_job * args.steps / max(wl, 1),
+            "w_flops_per_launch": fl_this * args.steps / max(wl, 1),
             "e_kernel_seconds": sum(s_["e_kernel_seconds"] for s_ in sts),
             "energy_seconds": sum(s_["seconds"] for s_ in sts),
         }
 
-    head = "fp64" if "fp64" in results else next(iter(results))
     r = results[head]
     achieved = r["w_flops_per_launch"] / (r["w_kernel_avg_ms"] * 1e-3) / 1e12
     out = {
@@ -323,20 +341,23 @@ def main() -> int:
                      "kernel": f"wbuild_kernel<{head}>",
                      "avg_launch_ms": round(r["w_kernel_avg_ms"], 4)},
     }
-    precs = {}
+    precs_out = {}
     for p_, rr in results.items():
         d = {"tflops": round(rr["tflops"], 4), "ms_per_step": round(rr["ms_per_step"], 3),
-             "E": rr["E"],
+             "triples": rr["triples"], "E": rr["E"],
              "w_kernel_tflops": round(rr["w_flops_per_launch"] / (rr["w_kernel_avg_ms"] * 1e-3) / 1e12, 3),
              "issued_mfma_tflops": round(ISSUED[p_] * rr["w_flops_per_launch"]
                                          / (rr["w_kernel_avg_ms"] * 1e-3) / 1e12, 3),
              "peak": PEAK_TFLOPS[p_]}
-        if p_ != "fp64" and "fp64" in results:
-            dE = abs(rr["E"] - results["fp64"]["E"])
+        if p_ != head and head == "fp64" and head_pt is not None:
+            # same triples in FP64, summed in list order from the FP64 run
+            E64 = float(np.sum(head_pt[:rr["triples"]]))
+            dE = abs(rr["E"] - E64)
+            d["E_fp64_same_triples"] = E64
             d["dE_vs_fp64"] = dE
-            d["dE_rel"] = dE / abs(results["fp64"]["E"])
-        precs[p_] = d
-    out["precisions"] = precs
+            d["dE_rel"] = dE / abs(E64)
+        precs_out[p_] = d
+    out["precisions"] = precs_out
     if not args.no_cpu:
         from paper_2512_01055_amd.inputs import triple_list
         tl = triple_list(o)

@@ -358,10 +358,9 @@ struct TimingEvents {
 double flops_per_triple(int o, int v) { return 12.0 * (double)v * v * v * ((double)v + o); }
 
 static int batch_size(const Job &J, Prec p, long ntr) {
-  const int bm = wbuild_bm();
-  const int nb = wbuild_pick_nb(J.vp);
-  const long mt = ((long)J.vp * J.vp + bm - 1) / bm;
-  const long nt = (J.vp + 16 * nb - 1) / (16 * nb);
+  const WConfig wc = wbuild_config(p, J.vp);
+  const long mt = ((long)J.vp * J.vp + wc.bm() - 1) / wc.bm();
+  const long nt = (J.vp + wc.bn() - 1) / wc.bn();
   const long tiles = 3 * mt * nt;
   long b = std::max(1L, (16384 + tiles - 1) / tiles);
   // W scratch for two batches in flight
@@ -484,10 +483,9 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
   if (!fly && !op.X) throw Fail(TE_EINVAL, "(vv|vo) slices are not resident");
 
   const int o = J.o, vp = J.vp;
-  const int bm = wbuild_bm();
-  const int nbk = wbuild_pick_nb(vp);
-  const int mt = (int)(((long)vp * vp + bm - 1) / bm);
-  const int nt = (vp + 16 * nbk - 1) / (16 * nbk);
+  const WConfig wc = wbuild_config(p, vp);
+  const int mt = (int)(((long)vp * vp + wc.bm() - 1) / wc.bm());
+  const int nt = (vp + wc.bn() - 1) / wc.bn();
   const int tiles = 3 * mt * nt;
   const int B = batch_size(J, p, ntr);
   const size_t vp3 = (size_t)vp * vp * vp;
@@ -578,7 +576,7 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
     if (fly) HIPCHK(hipEventRecord(ta.stop[b], J.s_aux));
     HIPCHK(hipEventRecord(tw.start[b], J.s_aux));
     HIPCHK(launch_wbuild(p, witems.as<WItem>() + first, nullptr, cnt, tiles, (long)cnt * tiles,
-                         nbk, J.s_aux));
+                         wc, J.s_aux));
     HIPCHK(hipEventRecord(tw.stop[b], J.s_aux));
     HIPCHK(hipEventRecord(J.ev_w[slot], J.s_aux));
     HIPCHK(hipStreamWaitEvent(J.s_main, J.ev_w[slot], 0));

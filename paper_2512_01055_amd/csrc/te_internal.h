@@ -65,11 +65,15 @@ struct GemmTN {
 };
 
 // Launchers (te_kernels.hip). All return the hipError_t of the launch.
+// W-build tile shape: BM = 64 wm rows (virtual pairs), BN = 16 nb columns.
+struct WConfig {
+  int nb = 5, wm = 2;
+  int bm() const { return 64 * wm; }
+  int bn() const { return 16 * nb; }
+};
+WConfig wbuild_config(Prec p, int vp);
 hipError_t launch_wbuild(Prec p, const WItem *d_items, const int *d_tile_item, int nitems,
-                         int tiles_per_item, long total_tiles, int bn_blocks,
-                         hipStream_t s);
-int wbuild_bm();
-int wbuild_pick_nb(int vp);
+                         int tiles_per_item, long total_tiles, WConfig cfg, hipStream_t s);
 hipError_t launch_energy(bool w_is_f64, const EItem *d_items, const int *d_blk_item,
                          int nitems, int blks_per_item, long total_blks, hipStream_t s);
 hipError_t launch_reduce(const RItem *d_items, int nitems, hipStream_t s);

@@ -22,7 +22,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int WG = 256;
-constexpr int BM = 128;  // virtual-pair rows per W-build tile (4 waves x 32)
 
 // ---------------------------------------------------------------- traits
 template <Prec P> struct Tr;
@@ -142,7 +141,9 @@ __device__ inline Setup make_setup(int g, int i, int j, int k) {
   return s;
 }
 
-template <Prec P, int NB>
+// NB: 16-column blocks per tile (BN = 16 NB); WM: 16-row blocks per wave
+// (BM = 4 waves x 16 WM rows).
+template <Prec P, int NB, int WM>
 __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ items,
                                                     const int *__restrict__ tile_item,
                                                     int tiles_per_item, long total_tiles) {
@@ -152,6 +153,7 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
   using Out = typename TR::Out;
   constexpr int KT = TR::KT, LD = TR::KT + TR::PAD, NP = TR::NP, KM = TR::KM;
   constexpr int BN = 16 * NB;
+  constexpr int BM = 64 * WM;
   constexpr int CPR = KT / 8;                     // 8-element chunks per row
   constexpr int CA = (BM * KT / 8 + WG - 1) / WG; // A chunks per thread
   constexpr int CB = (BN * KT / 8 + WG - 1) / WG; // B chunks per thread
@@ -349,15 +351,15 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
     }
   };
 
-  Acc acc[2][NB];
+  Acc acc[WM][NB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < WM; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
 
-  const int wrow = wave * 32;
+  const int wrow = wave * 16 * WM;
   const int fr = lane & 15;
   const int fk = lane >> 4;
 
@@ -371,19 +373,19 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
     for (int kk = 0; kk < KT / KM; ++kk) {
       if constexpr (NP == 1) {
         using E = T;
-        E av[2], bv[NB];
+        E av[WM], bv[NB];
 #pragma unroll
-        for (int rb_ = 0; rb_ < 2; ++rb_) av[rb_] = As[cur][0][wrow + rb_ * 16 + fr][kk * 4 + fk];
+        for (int rb_ = 0; rb_ < WM; ++rb_) av[rb_] = As[cur][0][wrow + rb_ * 16 + fr][kk * 4 + fk];
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) bv[cb] = Bs[cur][0][cb * 16 + fr][kk * 4 + fk];
 #pragma unroll
-        for (int rb_ = 0; rb_ < 2; ++rb_)
+        for (int rb_ = 0; rb_ < WM; ++rb_)
 #pragma unroll
           for (int cb = 0; cb < NB; ++cb) acc[rb_][cb] = mma(av[rb_], bv[cb], acc[rb_][cb]);
       } else {
-        bf8 av[2][NP], bv[NB][NP];
+        bf8 av[WM][NP], bv[NB][NP];
 #pragma unroll
-        for (int rb_ = 0; rb_ < 2; ++rb_)
+        for (int rb_ = 0; rb_ < WM; ++rb_)
 #pragma unroll
           for (int p = 0; p < NP; ++p)
             av[rb_][p] = *reinterpret_cast<const bf8 *>(&As[cur][p][wrow + rb_ * 16 + fr][fk * 8]);
@@ -393,7 +395,7 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
           for (int p = 0; p < NP; ++p)
             bv[cb][p] = *reinterpret_cast<const bf8 *>(&Bs[cur][p][cb * 16 + fr][fk * 8]);
 #pragma unroll
-        for (int rb_ = 0; rb_ < 2; ++rb_)
+        for (int rb_ = 0; rb_ < WM; ++rb_)
 #pragma unroll
           for (int cb = 0; cb < NB; ++cb) {
             // smallest cross products first: sum over pa + pb < NP
@@ -413,7 +415,7 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
   Out *Wg = reinterpret_cast<Out *>(w.W) + (long)g * vp2 * vp;
   const int nT = vp >> 3;
 #pragma unroll
-  for (int rb_ = 0; rb_ < 2; ++rb_)
+  for (int rb_ = 0; rb_ < WM; ++rb_)
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
@@ -693,11 +695,12 @@ __global__ void t2_asym_kernel(const double *__restrict__ t2, int o, int v,
 }  // namespace
 
 // ------------------------------------------------------------ launchers
-int wbuild_bm() { return BM; }
-
-// Columns per tile are 16*NB; choose NB in [4, 8] minimising padded waste of
-// the lone-index dimension, larger NB on ties.
-int wbuild_pick_nb(int vp) {
+// Tile shape per precision: rows per wave (WM) and the column-block count
+// NB in [4, 8] that minimises padded waste of the lone index (larger NB on
+// ties).
+WConfig wbuild_config(Prec p, int vp) {
+  WConfig c;
+  c.wm = (p == Prec::F64) ? 2 : 2;
   int best = 8;
   long best_w = -1;
   for (int nb = 8; nb >= 4; --nb) {
@@ -706,34 +709,45 @@ int wbuild_pick_nb(int vp) {
     long waste = tiles * bn - vp;
     if (best_w < 0 || waste < best_w) { best_w = waste; best = nb; }
   }
-  return best;
+  c.nb = best;
+  return c;
 }
 
-template <Prec P>
-static hipError_t launch_wb_p(const WItem *d_items, const int *d_tile_item, int tiles_per_item,
-                              long total, int nb, hipStream_t s) {
+template <Prec P, int WM>
+static hipError_t launch_wb_pw(const WItem *d_items, const int *d_tile_item, int tiles_per_item,
+                               long total, int nb, hipStream_t s) {
   dim3 grid((unsigned)total), block(WG);
   switch (nb) {
-    case 4: wbuild_kernel<P, 4><<<grid, block, 0, s>>>(d_items, d_tile_item, tiles_per_item, total); break;
-    case 5: wbuild_kernel<P, 5><<<grid, block, 0, s>>>(d_items, d_tile_item, tiles_per_item, total); break;
-    case 6: wbuild_kernel<P, 6><<<grid, block, 0, s>>>(d_items, d_tile_item, tiles_per_item, total); break;
-    case 7: wbuild_kernel<P, 7><<<grid, block, 0, s>>>(d_items, d_tile_item, tiles_per_item, total); break;
-    case 8: wbuild_kernel<P, 8><<<grid, block, 0, s>>>(d_items, d_tile_item, tiles_per_item, total); break;
+    case 4: wbuild_kernel<P, 4, WM><<<grid, block, 0, s>>>(d_items, d_tile_item, tiles_per_item, total); break;
+    case 5: wbuild_kernel<P, 5, WM><<<grid, block, 0, s>>>(d_items, d_tile_item, tiles_per_item, total); break;
+    case 6: wbuild_kernel<P, 6, WM><<<grid, block, 0, s>>>(d_items, d_tile_item, tiles_per_item, total); break;
+    case 7: wbuild_kernel<P, 7, WM><<<grid, block, 0, s>>>(d_items, d_tile_item, tiles_per_item, total); break;
+    case 8: wbuild_kernel<P, 8, WM><<<grid, block, 0, s>>>(d_items, d_tile_item, tiles_per_item, total); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <Prec P>
+static hipError_t launch_wb_p(const WItem *d_items, const int *d_tile_item, int tiles_per_item,
+                              long total, WConfig c, hipStream_t s) {
+  if (c.wm == 2) return launch_wb_pw<P, 2>(d_items, d_tile_item, tiles_per_item, total, c.nb, s);
+  if constexpr (P != Prec::BF16X3) {  // three BF16 parts of a 256-row tile exceed LDS
+    if (c.wm == 4) return launch_wb_pw<P, 4>(d_items, d_tile_item, tiles_per_item, total, c.nb, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_wbuild(Prec p, const WItem *d_items, const int *d_tile_item, int nitems,
-                         int tiles_per_item, long total_tiles, int nb, hipStream_t s) {
+                         int tiles_per_item, long total_tiles, WConfig c, hipStream_t s) {
   (void)nitems;
   if (total_tiles <= 0) return hipSuccess;
   if (total_tiles > 0x7fffffffL) return hipErrorInvalidValue;
   switch (p) {
-    case Prec::F64: return launch_wb_p<Prec::F64>(d_items, d_tile_item, tiles_per_item, total_tiles, nb, s);
-    case Prec::F32: return launch_wb_p<Prec::F32>(d_items, d_tile_item, tiles_per_item, total_tiles, nb, s);
-    case Prec::BF16X3: return launch_wb_p<Prec::BF16X3>(d_items, d_tile_item, tiles_per_item, total_tiles, nb, s);
-    case Prec::BF16X2: return launch_wb_p<Prec::BF16X2>(d_items, d_tile_item, tiles_per_item, total_tiles, nb, s);
+    case Prec::F64: return launch_wb_p<Prec::F64>(d_items, d_tile_item, tiles_per_item, total_tiles, c, s);
+    case Prec::F32: return launch_wb_p<Prec::F32>(d_items, d_tile_item, tiles_per_item, total_tiles, c, s);
+    case Prec::BF16X3: return launch_wb_p<Prec::BF16X3>(d_items, d_tile_item, tiles_per_item, total_tiles, c, s);
+    case Prec::BF16X2: return launch_wb_p<Prec::BF16X2>(d_items, d_tile_item, tiles_per_item, total_tiles, c, s);
   }
   return hipErrorInvalidValue;
 }

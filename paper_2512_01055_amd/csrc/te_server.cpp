@@ -257,7 +257,9 @@ bool ServerImpl::launch_round() {
       if (best < 0 || cols < best) { best = cols; nb = c; }
     }
   }
-  const int bm = wbuild_bm();
+  WConfig wc = wbuild_config(P, cand.front()->job->vp);
+  wc.nb = nb;
+  const int bm = wc.bm();
   struct Pick { SJob *j; long t; };
   std::vector<Pick> picks;
   long tiles = 0, blks = 0;
@@ -341,7 +343,7 @@ bool ServerImpl::launch_round() {
   HIPCHK(hipMemcpyAsync(S.eitems.p, S.h_ei, n * sizeof(EItem), hipMemcpyHostToDevice, s_w));
   HIPCHK(hipMemcpyAsync(S.ritems.p, S.h_ri, n * sizeof(RItem), hipMemcpyHostToDevice, s_w));
   HIPCHK(hipMemcpyAsync(S.bmap.p, S.h_bmap, (b0 + n) * sizeof(int), hipMemcpyHostToDevice, s_w));
-  HIPCHK(launch_wbuild(P, S.witems.as<WItem>(), S.tmap.as<int>(), n, 0, t0, nb, s_w));
+  HIPCHK(launch_wbuild(P, S.witems.as<WItem>(), S.tmap.as<int>(), n, 0, t0, wc, s_w));
   HIPCHK(hipEventRecord(S.ev_w, s_w));
   HIPCHK(hipStreamWaitEvent(s_e, S.ev_w, 0));
   HIPCHK(launch_energy(P == Prec::F64, S.eitems.as<EItem>(), S.bmap.as<int>(), n, 0, b0, s_e));
@@ -555,7 +557,7 @@ te_status te_submit(te_server srv, const te_problem *prob, te_precision prec, ui
     return set_error(TE_ENOMEM, "job footprint " + std::to_string(fp) +
                                     " bytes can never fit the server budget");
   {
-    const size_t bm = wbuild_bm(), nT = vp / BOX;
+    const size_t bm = 128, nT = vp / BOX;   // smallest tile shape any precision uses
     const size_t tiles = 3 * ((vp * vp + bm - 1) / bm) * ((vp + 63) / 64);
     if (tiles > (size_t)MAX_TILES || nT * (nT + 1) * (nT + 2) / 6 > (size_t)MAX_BLKS)
       return set_error(TE_ENOMEM, "one triple of this job exceeds a server round");

@@ -80,3 +80,23 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(te, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no fallback"):
         te.lib()
+
+
+def test_slice_plan_counts():
+    """On-the-fly schedule: a cache holding every slice assembles each once;
+    smaller caches need more assemblies, never fewer than o."""
+    lib = te.lib()
+    for o in (3, 7, 20, 40):
+        assert lib.te_plan_slice_loads(o, o, 1) == o
+        assert lib.te_plan_slice_loads(o, o + 5, 64) == o
+        prev = None
+        for S in range(3, o + 1):
+            n = lib.te_plan_slice_loads(o, S, 1)
+            assert n >= o
+            if prev is not None:
+                assert n <= prev * 1.5 + 3        # no blow-up when the cache grows
+            prev = n
+    # blocked order keeps the o=100 schedule near o^3 / (6 (S/3)^2) block changes
+    assert lib.te_plan_slice_loads(100, 45, 1) < 2000
+    assert lib.te_plan_slice_loads(0, 10, 1) == -1
+    assert lib.te_plan_slice_loads(10, 2, 1) == -1
