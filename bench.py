@@ -156,7 +156,7 @@ def bench_serving(args) -> int:
 
     def run_srv(arrivals):
         lat = [None] * len(os_)
-        with te.Server(device=0) as srv:
+        with te.Server(device=0, borrow_inputs=True, staging_threads=args.staging_threads) as srv:
             t_start = time.perf_counter()
             tickets = []
             for q, (o, a) in enumerate(zip(os_, arrivals)):
@@ -225,6 +225,7 @@ def main() -> int:
     ap.add_argument("--omin", type=int, default=8)
     ap.add_argument("--omax", type=int, default=40)
     ap.add_argument("--precision", default="fp64", help="serving: precision of every job")
+    ap.add_argument("--staging-threads", type=int, default=2, help="serving: concurrent staging")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size copy "
                          "kernel for scaling hardware byte counters)")

@@ -165,11 +165,17 @@ typedef struct te_server_config {
   size_t hbm_budget;      /* bytes for resident jobs; 0: 80% of free memory */
   int max_resident_jobs;  /* 0: 64                                           */
   int max_queued_jobs;    /* 0: 4096                                         */
+  int borrow_inputs;      /* 0: te_submit copies the host arrays before it
+                             returns; 1: it keeps the pointers, and the
+                             caller keeps the arrays alive and unchanged
+                             until the job's final te_poll / te_wait        */
+  int staging_threads;    /* jobs staged concurrently; 0: 2                  */
 } te_server_config;
 
 te_status te_server_create(const te_server_config *cfg, te_server *out);
-/* Copies the problem (host memory only) and queues it. Returns TE_ENOMEM if
- * the job could never fit the budget, TE_EBUSY if the queue is full. */
+/* Queues a problem in host memory (copied, or borrowed with borrow_inputs).
+ * Returns TE_ENOMEM if the job could never fit the budget, TE_EBUSY if the
+ * queue is full. */
 te_status te_submit(te_server srv, const te_problem *prob, te_precision prec,
                     uint64_t *ticket);
 /* TE_PENDING while queued or running; the job's final status otherwise

@@ -6,7 +6,7 @@
 // of resident jobs), and their occupied triples are packed with those of every
 // other resident job of the same precision into shared launches: one W-build
 // launch and one energy launch per round, mapping tiles and sextet blocks to
-// (job, triple) items. Two rounds are in flight at once (two scratch slots).
+// (job, triple) items. Three rounds are in flight at once (three scratch slots).
 // A job finishes with a fixed-order sum of its per-triple partials, so its
 // result is bitwise the one te_energy computes for it alone.
 #include <hip/hip_runtime.h>
@@ -32,10 +32,12 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 
-// Host copy of a submitted problem (te_submit returns before staging).
+// Host copy of a submitted problem (te_submit returns before staging), or
+// the caller's pointers when the server borrows its inputs.
 struct HostCopy {
   te_problem p{};
   std::vector<double> a[10];
+  void borrow(const te_problem &src) { p = src; }
   void take(const te_problem &src) {
     p = src;
     p.mem = TE_MEM_HOST;
@@ -92,6 +94,7 @@ struct SJob {
 // Per-round limits. te_submit rejects jobs whose single triple would
 // exceed them, so every round can hold at least one item.
 constexpr int MAX_ITEMS = 4096;
+constexpr int NSLOT = 3;   // rounds in flight
 constexpr long MAX_TILES = 262144;
 constexpr long MAX_BLKS = 4L << 20;
 
@@ -111,9 +114,12 @@ struct ServerImpl {
   int device = 0;
   size_t budget = 0, wcap = 0;
   int max_resident = 64, max_queued = 4096;
+  bool borrow = false;
+  int nstage = 2;
   Arena arena;
-  hipStream_t s_w = nullptr, s_e = nullptr, s_stage = nullptr;
-  Slot slot[2];
+  hipStream_t s_w = nullptr, s_e = nullptr;
+  std::vector<hipStream_t> s_stage;   // one staging stream per staging thread
+  Slot slot[NSLOT];
   long round = 0;
 
   std::mutex mu;
@@ -126,14 +132,16 @@ struct ServerImpl {
   std::unordered_map<uint64_t, std::unique_ptr<SJob>> jobs;
   size_t reserved = 0;              // footprints of admitted jobs
   uint64_t retired = 0;             // jobs retired so far
-  std::thread sched, stager;
+  std::thread sched;
+  std::vector<std::thread> stagers;
   std::string fatal;
 
   void start();
   void shutdown();
-  void stage_loop();
+  void stage_loop(int q);
   void sched_loop();
-  bool launch_round();
+  enum class Launch { Done, NoWork, SlotBusy };
+  Launch launch_round();
   void retire();
   void finish_job(SJob *j, te_status s, const std::string &msg);
 };
@@ -146,8 +154,9 @@ void ServerImpl::finish_job(SJob *j, te_status s, const std::string &msg) {
 }
 
 // Staging thread: admits jobs in arrival order while their footprint fits.
-void ServerImpl::stage_loop() {
+void ServerImpl::stage_loop(int q) {
   HIPCHK(hipSetDevice(device));
+  hipStream_t ss = s_stage[q];
   for (;;) {
     SJob *j = nullptr;
     {
@@ -172,7 +181,7 @@ void ServerImpl::stage_loop() {
     try {
       JobOpts jo;
       jo.arena = &arena;
-      jo.stream = s_stage;
+      jo.stream = ss;
       jo.budget = j->footprint;
       jo.drop_fp64_x = true;
       jo.prec = j->prec;
@@ -183,7 +192,7 @@ void ServerImpl::stage_loop() {
       Job &J = *j->job;
       jalloc(J, j->eout, (size_t)j->ntr * 8);
       jalloc(J, j->esum, 8);
-      HIPCHK(hipStreamSynchronize(s_stage));
+      HIPCHK(hipStreamSynchronize(ss));
       J.s_main = nullptr;  // the job's device work is tracked by server events from now on
       j->hc.drop();
     } catch (const Fail &f) {
@@ -223,12 +232,11 @@ void ServerImpl::stage_loop() {
   }
 }
 
-// Build and launch one packed round into a free slot; false if there is no
-// work or no free slot.
-bool ServerImpl::launch_round() {
-  Slot &S = slot[round & 1];
+// Build and launch one packed round into the next slot.
+ServerImpl::Launch ServerImpl::launch_round() {
+  Slot &S = slot[round % NSLOT];
   if (S.busy) {
-    if (hipEventQuery(S.ev_e) != hipSuccess) return false;
+    if (hipEventQuery(S.ev_e) != hipSuccess) return Launch::SlotBusy;
     S.busy = false;
   }
   std::vector<SJob *> cand;
@@ -241,7 +249,7 @@ bool ServerImpl::launch_round() {
         if (j->prec == P) cand.push_back(j);
       }
   }
-  if (cand.empty()) return false;
+  if (cand.empty()) return Launch::NoWork;
 
   const int osz = out_bytes(P);
   // column-block width minimising the padded lone-index work of the round
@@ -290,7 +298,7 @@ bool ServerImpl::launch_round() {
   }
   for (SJob *j : cand)
     while (j->next < j->ntr && fits(j)) take(j);
-  if (picks.empty()) return false;
+  if (picks.empty()) return Launch::NoWork;
 
   // items and maps in pinned memory
   const int n = (int)picks.size();
@@ -363,7 +371,7 @@ bool ServerImpl::launch_round() {
   HIPCHK(hipEventRecord(S.ev_e, s_e));
   S.busy = true;
   round++;
-  return true;
+  return Launch::Done;
 }
 
 void ServerImpl::retire() {
@@ -403,10 +411,15 @@ void ServerImpl::sched_loop() {
     HIPCHK(hipSetDevice(device));
     for (;;) {
       retire();
-      bool launched = launch_round();
+      const Launch l = launch_round();
+      if (l == Launch::SlotBusy) {
+        // every slot is queued on the device: block until the oldest drains,
+        // then fill it at once (no polling gap between rounds)
+        HIPCHK(hipEventSynchronize(slot[round % NSLOT].ev_e));
+      }
       std::unique_lock<std::mutex> lk(mu);
       if (stop) break;
-      if (!launched) cv.wait_for(lk, std::chrono::microseconds(200));
+      if (l == Launch::NoWork) cv.wait_for(lk, std::chrono::microseconds(200));
     }
   } catch (const Fail &f) {
     std::lock_guard<std::mutex> lk(mu);
@@ -421,7 +434,8 @@ void ServerImpl::start() {
   HIPCHK(hipSetDevice(device));
   HIPCHK(hipStreamCreateWithFlags(&s_w, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&s_e, hipStreamNonBlocking));
-  HIPCHK(hipStreamCreateWithFlags(&s_stage, hipStreamNonBlocking));
+  s_stage.assign(nstage, nullptr);
+  for (auto &st : s_stage) HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   wcap = std::min<size_t>((size_t)3 << 30, budget / 8);
   for (Slot &S : slot) {
     S.W.alloc(wcap, nullptr, 0);
@@ -439,11 +453,11 @@ void ServerImpl::start() {
     HIPCHK(hipEventCreateWithFlags(&S.ev_w, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&S.ev_e, hipEventDisableTiming));
   }
-  const size_t scratch = 2 * (wcap + MAX_BLKS * 8 + (MAX_BLKS + MAX_ITEMS) * 4);
+  const size_t scratch = NSLOT * (wcap + MAX_BLKS * 8 + (MAX_BLKS + MAX_ITEMS) * 4);
   if (budget <= scratch + ((size_t)1 << 28))
     throw Fail(TE_ENOMEM, "HBM budget too small for the server's round scratch");
   arena.init(budget - scratch);
-  stager = std::thread([this] { stage_loop(); });
+  for (int q = 0; q < nstage; ++q) stagers.emplace_back([this, q] { stage_loop(q); });
   sched = std::thread([this] { sched_loop(); });
 }
 
@@ -453,12 +467,14 @@ void ServerImpl::shutdown() {
     stop = true;
   }
   cv.notify_all();
-  if (stager.joinable()) stager.join();
+  for (auto &t : stagers)
+    if (t.joinable()) t.join();
   if (sched.joinable()) sched.join();
   (void)hipSetDevice(device);
   if (s_w) (void)hipStreamSynchronize(s_w);
   if (s_e) (void)hipStreamSynchronize(s_e);
-  if (s_stage) (void)hipStreamSynchronize(s_stage);
+  for (auto st : s_stage)
+    if (st) (void)hipStreamSynchronize(st);
   {
     std::lock_guard<std::mutex> lk(mu);
     for (auto &kv : jobs) {
@@ -488,7 +504,8 @@ void ServerImpl::shutdown() {
   arena.destroy();
   if (s_w) (void)hipStreamDestroy(s_w);
   if (s_e) (void)hipStreamDestroy(s_e);
-  if (s_stage) (void)hipStreamDestroy(s_stage);
+  for (auto st : s_stage)
+    if (st) (void)hipStreamDestroy(st);
 }
 
 }  // namespace te
@@ -523,6 +540,10 @@ te_status te_server_create(const te_server_config *cfg_in, te_server *out) {
   if (S->budget > freeb) return set_error(TE_ENOMEM, "HBM budget exceeds free device memory");
   S->max_resident = cfg.max_resident_jobs ? cfg.max_resident_jobs : 64;
   S->max_queued = cfg.max_queued_jobs ? cfg.max_queued_jobs : 4096;
+  S->borrow = cfg.borrow_inputs != 0;
+  if (cfg.staging_threads < 0 || cfg.staging_threads > 16)
+    return set_error(TE_EINVAL, "staging_threads must be in [0, 16]");
+  S->nstage = cfg.staging_threads ? cfg.staging_threads : 2;
   try {
     S->start();
   } catch (...) {
@@ -573,7 +594,10 @@ te_status te_submit(te_server srv, const te_problem *prob, te_precision prec, ui
   j->prec = P;
   j->o = prob->o; j->v = prob->v; j->naux = prob->naux;
   j->footprint = fp;
-  j->hc.take(*prob);
+  if (S.borrow)
+    j->hc.borrow(*prob);
+  else
+    j->hc.take(*prob);
   j->trip = triple_list_host(prob->o);
   j->ntr = (long)j->trip.size() / 3;
   HIPCHK(hipSetDevice(S.device));

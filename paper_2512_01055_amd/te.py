@@ -54,7 +54,8 @@ class Stats(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("device", C.c_int), ("hbm_budget", C.c_size_t),
-                ("max_resident_jobs", C.c_int), ("max_queued_jobs", C.c_int)]
+                ("max_resident_jobs", C.c_int), ("max_queued_jobs", C.c_int),
+                ("borrow_inputs", C.c_int), ("staging_threads", C.c_int)]
 
 
 _lib: Optional[C.CDLL] = None
@@ -249,12 +250,14 @@ class Server:
     """Continuous-batching (T) server (te_server_*)."""
 
     def __init__(self, device: int = 0, hbm_budget: int = 0, max_resident_jobs: int = 0,
-                 max_queued_jobs: int = 0):
+                 max_queued_jobs: int = 0, borrow_inputs: bool = False, staging_threads: int = 0):
         L = lib()
-        cfg = ServerConfig(device, hbm_budget, max_resident_jobs, max_queued_jobs)
+        cfg = ServerConfig(device, hbm_budget, max_resident_jobs, max_queued_jobs,
+                           int(borrow_inputs), staging_threads)
         h = C.c_void_p()
         _check(L.te_server_create(C.byref(cfg), C.byref(h)))
         self._h = h
+        self._borrowed = {}        # ticket -> arrays kept alive while the job runs
 
     def submit(self, prob, precision: str = "fp64") -> int:
         p, arrs = make_problem_struct(prob, int(prob.o), int(prob.v), int(prob.naux))
@@ -262,25 +265,35 @@ class Server:
             raise ValueError("te_submit takes host arrays")
         t = C.c_uint64()
         _check(lib().te_submit(self._h, C.byref(p), PRECISIONS[precision], C.byref(t)))
+        self._borrowed[t.value] = arrs
         return t.value
 
     def poll(self, ticket: int):
         """None while pending, else (E, stats)."""
         e, st = C.c_double(), Stats()
-        s = _check(lib().te_poll(self._h, ticket, C.byref(e), C.byref(st)))
+        try:
+            s = _check(lib().te_poll(self._h, ticket, C.byref(e), C.byref(st)))
+        except TeError:
+            self._borrowed.pop(ticket, None)
+            raise
         if s == PENDING:
             return None
+        self._borrowed.pop(ticket, None)
         return e.value, st.as_dict()
 
     def wait(self, ticket: int):
         e, st = C.c_double(), Stats()
-        _check(lib().te_wait(self._h, ticket, C.byref(e), C.byref(st)))
+        try:
+            _check(lib().te_wait(self._h, ticket, C.byref(e), C.byref(st)))
+        finally:
+            self._borrowed.pop(ticket, None)
         return e.value, st.as_dict()
 
     def close(self) -> None:
         if getattr(self, "_h", None):
             _check(lib().te_server_destroy(self._h))
             self._h = None
+            self._borrowed = {}
 
     def __enter__(self):
         return self

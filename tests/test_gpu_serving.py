@@ -61,14 +61,14 @@ def test_admission_one_resident_job_at_a_time():
     assert got == alone
 
 
-# 512 MiB: round scratch takes a quarter plus ~100 MiB, the arena keeps
-# ~290 MiB, room for one o=12 v=104 job (~180 MiB) at a time
-TIGHT = 512 << 20
+# 1 GiB: three round-scratch slots take ~530 MiB, the arena keeps ~490 MiB,
+# room for one o=14 v=128 job (~350 MiB) at a time
+TIGHT = 1 << 30
 
 
 def test_admission_under_tight_budget():
     te = _te()
-    probs = [make_problem(12, 104, 312, 210 + q) for q in range(3)]
+    probs = [make_problem(14, 128, 384, 210 + q) for q in range(3)]
     alone = [_alone(te, P, "fp64") for P in probs]
     with te.Server(device=0, hbm_budget=TIGHT) as srv:
         tickets = [srv.submit(P, "fp64") for P in probs]
@@ -123,3 +123,13 @@ def test_o_equal_one_finishes_with_zero():
         t = srv.submit(make_problem(1, 16, 20, 500), "fp64")
         E, st = srv.wait(t)
     assert E == 0.0 and st["n_triples"] == 0
+
+
+def test_borrowed_inputs_and_parallel_staging():
+    te = _te()
+    probs = [make_problem(*m) for m in MIX]
+    alone = [_alone(te, P, "fp64") for P in probs]
+    with te.Server(device=0, borrow_inputs=True, staging_threads=3) as srv:
+        tickets = [srv.submit(P, "fp64") for P in probs]
+        got = [srv.wait(t)[0] for t in tickets]
+    assert got == alone
