@@ -215,7 +215,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--secondary-frac", type=float, default=0.1,
                     help="fraction of the triple list (leading slice) the non-FP64 precisions time")
-    ap.add_argument("--cpu-triples", type=int, default=2)
+    ap.add_argument("--cpu-triples", type=int, default=4)
     ap.add_argument("--max-triples", type=int, default=0,
                     help="exploration only: evaluate the first N triples per step")
     ap.add_argument("--workload", choices=("large", "huge", "serving"), default="large")
@@ -340,7 +340,8 @@ def main() -> int:
                      "traffic": measured_traffic(f"wbuild_kernel<{head}>", f"o{o}_v{v}"),
                      "traffic_unit": "bytes/launch",
                      "kernel": f"wbuild_kernel<{head}>",
-                     "avg_launch_ms": round(r["w_kernel_avg_ms"], 4)},
+                     "avg_launch_ms": round(r["w_kernel_avg_ms"], 4),
+                     "sustained_mfma_tflops": round(te.mfma_sustained(head if head != "bf16x2" else "bf16x3", 2.0), 2)},
     }
     precs_out = {}
     for p_, rr in results.items():

@@ -187,6 +187,14 @@ te_status te_wait(te_server srv, uint64_t ticket, double *e_t, te_stats *st);
 /* Stops the server; jobs not yet finished end with TE_ECANCELED. */
 te_status te_server_destroy(te_server srv);
 
+/* Diagnostic: the sustained matrix-core rate of `device` for the MFMA form
+ * the W build uses in `prec` (FP64, FP32 or BF16 16x16 blocks), measured
+ * with a register-only kernel that keeps every SIMD issuing independent
+ * MFMA chains for about `seconds`. Puts a kernel's fraction of the published
+ * peak in context (clocks under sustained matrix load sit below the peak
+ * clock). Writes TFLOP/s of the instruction itself (for BF16: per product). */
+te_status te_mfma_sustained(int device, te_precision prec, double seconds, double *tflops);
+
 const char *te_strerror(te_status s);
 const char *te_last_error(void);
 

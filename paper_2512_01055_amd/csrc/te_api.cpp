@@ -861,6 +861,46 @@ int64_t te_plan_slice_loads(int32_t o, int32_t cache_slices, int32_t batch) {
   }
 }
 
+te_status te_mfma_sustained(int device, te_precision prec, double seconds, double *tflops) {
+  TE_GUARD_BEGIN
+  if (!tflops || !(seconds > 0.0) || seconds > 60.0)
+    return set_error(TE_EINVAL, "need a result pointer and 0 < seconds <= 60");
+  Prec p = to_prec(prec);
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return set_error(TE_EINVAL, "bad device ordinal");
+  HIPCHK(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  const int blocks = 8 * prop.multiProcessorCount;   // 8 waves per SIMD
+  DBuf out;
+  out.alloc((size_t)blocks * 256 * 8, nullptr, 0);
+  hipStream_t s;
+  HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double fl = 0, rate = 0;
+  int iters = 256;
+  float ms = 0.f;
+  for (int rep = 0; rep < 8; ++rep) {     // grow the loop until it runs `seconds`
+    HIPCHK(hipEventRecord(e0, s));
+    HIPCHK(launch_mfma_probe(p, out.p, blocks, iters, s, &fl));
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    rate = fl / (ms * 1e-3) / 1e12;
+    if (ms * 1e-3 >= 0.5 * seconds) break;
+    iters = (int)std::min(1e8, iters * std::max(2.0, seconds / std::max(ms * 1e-3, 1e-4)));
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  *tflops = rate;
+  return TE_OK;
+  TE_GUARD_END
+}
+
 const char *te_strerror(te_status s) {
   switch (s) {
     case TE_OK: return "ok";

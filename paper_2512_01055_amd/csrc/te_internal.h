@@ -85,6 +85,8 @@ hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t s)
 hipError_t launch_to_bf16_parts(const double *src, uint16_t *dst, size_t n, int nparts,
                                 hipStream_t s);
 hipError_t launch_check(const double *x, size_t n, int *flag, hipStream_t s);
+hipError_t launch_mfma_probe(Prec p, void *out, int blocks, int iters, hipStream_t s,
+                             double *flops);
 hipError_t launch_t2_asym(const double *t2, int o, int v, double *maxdiff, double *maxabs,
                           hipStream_t s);
 

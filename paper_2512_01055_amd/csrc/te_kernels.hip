@@ -28,22 +28,38 @@ template <Prec P> struct Tr;
 // Output lane layout of the 16x16 MFMA blocks: lane l, register r holds
 // column l%16 and row  (l/16) + 4r  for v_mfma_f64_16x16x4f64  (ROWQ = 1),
 //                      4(l/16) + r  for the FP32 and BF16 forms (ROWQ = 4).
+//
+// LDS rows of FP64/FP32 tiles are padded by one element so that the 16 rows a
+// fragment read touches fall in distinct banks. BF16 tiles (32 elements =
+// four 16-byte chunks per row) are unpadded and instead store chunk c of row
+// r at chunk c ^ ((r >> 2) & 3), which spreads the same reads over all banks
+// and saves the LDS that lets two workgroups share a CU.
 template <> struct Tr<Prec::F64> {
   using T = double; using Acc = d4; using Out = double;
   static constexpr int KT = 16, PAD = 1, NP = 1, KM = 4, ROWQ = 1;
+  static constexpr bool SWZ = false;
 };
 template <> struct Tr<Prec::F32> {
   using T = float; using Acc = f4; using Out = float;
   static constexpr int KT = 32, PAD = 1, NP = 1, KM = 4, ROWQ = 4;
+  static constexpr bool SWZ = false;
 };
 template <> struct Tr<Prec::BF16X3> {
   using T = uint16_t; using Acc = f4; using Out = float;
-  static constexpr int KT = 32, PAD = 8, NP = 3, KM = 32, ROWQ = 4;
+  static constexpr int KT = 32, PAD = 0, NP = 3, KM = 32, ROWQ = 4;
+  static constexpr bool SWZ = true;
 };
 template <> struct Tr<Prec::BF16X2> {
   using T = uint16_t; using Acc = f4; using Out = float;
-  static constexpr int KT = 32, PAD = 8, NP = 2, KM = 32, ROWQ = 4;
+  static constexpr int KT = 32, PAD = 0, NP = 2, KM = 32, ROWQ = 4;
+  static constexpr bool SWZ = true;
 };
+
+// Column of element k of LDS row r (see the layout note above).
+template <typename TR> __device__ inline int lcol(int r, int k) {
+  if constexpr (TR::SWZ) return (((k >> 3) ^ ((r >> 2) & 3)) << 3) | (k & 7);
+  else return k;
+}
 
 // Global-address-space views. Operand pointers reach the kernels through
 // item structs in memory, so the compiler sees generic pointers and would
@@ -311,7 +327,7 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
 #pragma unroll
           for (int p = 0; p < NP; ++p) {
             if constexpr (TR::PAD % 8 == 0) {
-              *reinterpret_cast<Chunk<T> *>(&As[buf][p][row][kcA[u]]) = ra[u][p];
+              *reinterpret_cast<Chunk<T> *>(&As[buf][p][row][lcol<TR>(row, kcA[u])]) = ra[u][p];
             } else {
 #pragma unroll
               for (int e = 0; e < 8; ++e) As[buf][p][row][kcA[u] + e] = ra[u][p].get(e);
@@ -329,7 +345,7 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
 #pragma unroll
           for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) As[buf][p][mc + e][kk] = ra[u][p].get(e);
+            for (int e = 0; e < 8; ++e) As[buf][p][mc + e][lcol<TR>(mc + e, kk)] = ra[u][p].get(e);
         }
       }
     }
@@ -341,7 +357,7 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
           if constexpr (TR::PAD % 8 == 0) {
-            *reinterpret_cast<Chunk<T> *>(&Bs[buf][p][row][kcB[u]]) = rb[u][p];
+            *reinterpret_cast<Chunk<T> *>(&Bs[buf][p][row][lcol<TR>(row, kcB[u])]) = rb[u][p];
           } else {
 #pragma unroll
             for (int e = 0; e < 8; ++e) Bs[buf][p][row][kcB[u] + e] = rb[u][p].get(e);
@@ -388,12 +404,13 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
         for (int rb_ = 0; rb_ < WM; ++rb_)
 #pragma unroll
           for (int p = 0; p < NP; ++p)
-            av[rb_][p] = *reinterpret_cast<const bf8 *>(&As[cur][p][wrow + rb_ * 16 + fr][fk * 8]);
+            av[rb_][p] = *reinterpret_cast<const bf8 *>(
+                &As[cur][p][wrow + rb_ * 16 + fr][lcol<TR>(wrow + rb_ * 16 + fr, fk * 8)]);
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
           for (int p = 0; p < NP; ++p)
-            bv[cb][p] = *reinterpret_cast<const bf8 *>(&Bs[cur][p][cb * 16 + fr][fk * 8]);
+            bv[cb][p] = *reinterpret_cast<const bf8 *>(&Bs[cur][p][cb * 16 + fr][lcol<TR>(cb * 16 + fr, fk * 8)]);
 #pragma unroll
         for (int rb_ = 0; rb_ < WM; ++rb_)
 #pragma unroll
@@ -692,7 +709,64 @@ __global__ void t2_asym_kernel(const double *__restrict__ t2, int o, int v,
   atomicMax(&out[1], (unsigned long long)__double_as_longlong(ma));
 }
 
+// ------------------------------------------------------------ MFMA rate probe
+// Eight independent accumulator chains per wave, operands in registers: the
+// matrix pipe never waits for memory. The result is written so the chains
+// are not optimised away.
+template <typename V, typename A, int NCH>
+__device__ inline void mfma_chains(V x, V y, A *acc, int iters) {
+  for (int it = 0; it < iters; ++it)
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = mma(x, y, acc[c]);
+}
+
+__global__ __launch_bounds__(WG) void probe_f64(double *out, int iters) {
+  d4 acc[8];
+  for (int c = 0; c < 8; ++c) acc[c] = d4{0, 0, 0, 0};
+  const double x = 1.0 + 1e-9 * threadIdx.x, y = 1.0 - 1e-9 * threadIdx.x;
+  mfma_chains<double, d4, 8>(x, y, acc, iters);
+  double s = 0;
+  for (int c = 0; c < 8; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  gst(out + blockIdx.x * (long)WG + threadIdx.x, s);
+}
+
+__global__ __launch_bounds__(WG) void probe_f32(float *out, int iters) {
+  f4 acc[8];
+  for (int c = 0; c < 8; ++c) acc[c] = f4{0, 0, 0, 0};
+  const float x = 1.0f + 1e-6f * threadIdx.x, y = 1.0f;
+  mfma_chains<float, f4, 8>(x, y, acc, iters);
+  float s = 0;
+  for (int c = 0; c < 8; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  gst(out + blockIdx.x * (long)WG + threadIdx.x, s);
+}
+
+__global__ __launch_bounds__(WG) void probe_bf16(float *out, int iters) {
+  f4 acc[8];
+  for (int c = 0; c < 8; ++c) acc[c] = f4{0, 0, 0, 0};
+  bf8 x, y;
+  for (int e = 0; e < 8; ++e) {
+    x[e] = (__bf16)(float)((threadIdx.x + e) & 7);
+    y[e] = (__bf16)(float)(e - 3);
+  }
+  mfma_chains<bf8, f4, 8>(x, y, acc, iters);
+  float s = 0;
+  for (int c = 0; c < 8; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  gst(out + blockIdx.x * (long)WG + threadIdx.x, s);
+}
+
 }  // namespace
+
+// flops of one probe launch: blocks x 4 waves x 8 chains x iters x MFMA flops
+hipError_t launch_mfma_probe(Prec p, void *out, int blocks, int iters, hipStream_t s,
+                             double *flops) {
+  const double per = p == Prec::F64 ? 2.0 * 16 * 16 * 4 : (p == Prec::F32 ? 2.0 * 16 * 16 * 4
+                                                                           : 2.0 * 16 * 16 * 32);
+  *flops = per * 8.0 * iters * blocks * (WG / 64);
+  if (p == Prec::F64) probe_f64<<<blocks, WG, 0, s>>>((double *)out, iters);
+  else if (p == Prec::F32) probe_f32<<<blocks, WG, 0, s>>>((float *)out, iters);
+  else probe_bf16<<<blocks, WG, 0, s>>>((float *)out, iters);
+  return hipGetLastError();
+}
 
 // ------------------------------------------------------------ launchers
 // Tile shape per precision: rows per wave (WM) and the column-block count

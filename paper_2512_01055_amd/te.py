@@ -94,6 +94,8 @@ def lib() -> C.CDLL:
     L.te_flops_per_triple.restype = C.c_double
     L.te_plan_slice_loads.argtypes = [C.c_int32, C.c_int32, C.c_int32]
     L.te_plan_slice_loads.restype = C.c_int64
+    L.te_mfma_sustained.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double)]
+    L.te_mfma_sustained.restype = C.c_int
     L.te_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(P)]
     L.te_submit.argtypes = [P, C.POINTER(Problem), S, C.POINTER(C.c_uint64)]
     L.te_poll.argtypes = [P, C.c_uint64, C.POINTER(C.c_double), C.POINTER(Stats)]
@@ -244,6 +246,13 @@ def triple_list(o: int) -> np.ndarray:
 
 def flops_per_triple(o: int, v: int) -> float:
     return float(lib().te_flops_per_triple(o, v))
+
+
+def mfma_sustained(precision: str = "fp64", seconds: float = 1.0, device: int = 0) -> float:
+    """Sustained MFMA TFLOP/s of the device for the W build's instruction."""
+    r = C.c_double()
+    _check(lib().te_mfma_sustained(device, PRECISIONS[precision], seconds, C.byref(r)))
+    return r.value
 
 
 class Server:
