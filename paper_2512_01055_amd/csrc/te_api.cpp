@@ -298,6 +298,7 @@ const Operands &ensure_prec(Job &J, Prec p) {
   const size_t nX = J.X.p ? (size_t)o * vp * vp * vp : 0;
   if (p != Prec::F64 && !J.X.p && J.x_resident)
     throw Fail(TE_EINVAL, "the FP64 (vv|vo) copy was released; precision cannot change");
+  op.lo = o;
   if (p == Prec::F64) {
     if (!J.X.p && J.x_resident)
       throw Fail(TE_EINVAL, "the FP64 (vv|vo) copy was released; precision cannot change");
@@ -315,16 +316,23 @@ const Operands &ensure_prec(Job &J, Prec p) {
     op.X = op.X_own.p; op.T2 = op.T2_own.p; op.In = op.In_own.p;
     op.xps = nX; op.tps = nT2; op.ips = nIn;
   } else {
+    // BF16 parts; the occupied-index operands get l last and padded to 8 so
+    // the W build loads them as 16-byte chunks
+    const int lo = (o + 7) / 8 * 8;
+    const size_t nInP = (size_t)o * vp * o * lo, nT2T = (size_t)o * vp * vp * lo;
     jalloc(J, op.T2_own, nT2 * 2 * 3);
-    jalloc(J, op.In_own, nIn * 2 * 3);
+    jalloc(J, op.In_own, nInP * 2 * 3);
+    jalloc(J, op.T2T_own, nT2T * 2 * 3);
     HIPCHK(launch_to_bf16_parts(J.t2, op.T2_own.as<uint16_t>(), nT2, 3, J.s_main));
-    HIPCHK(launch_to_bf16_parts(J.In.as<double>(), op.In_own.as<uint16_t>(), nIn, 3, J.s_main));
+    HIPCHK(launch_in_bf16_parts(J.In.as<double>(), op.In_own.as<uint16_t>(), o, vp, lo, 3,
+                                J.s_main));
+    HIPCHK(launch_t2t_bf16_parts(J.t2, op.T2T_own.as<uint16_t>(), o, vp, lo, 3, J.s_main));
     if (nX) {
       jalloc(J, op.X_own, nX * 2 * 3);
       HIPCHK(launch_to_bf16_parts(J.X.as<double>(), op.X_own.as<uint16_t>(), nX, 3, J.s_main));
     }
-    op.X = op.X_own.p; op.T2 = op.T2_own.p; op.In = op.In_own.p;
-    op.xps = nX; op.tps = nT2; op.ips = nIn;
+    op.X = op.X_own.p; op.T2 = op.T2_own.p; op.In = op.In_own.p; op.T2T = op.T2T_own.p;
+    op.xps = nX; op.tps = nT2; op.ips = nInP; op.t2tps = nT2T; op.lo = lo;
   }
   HIPCHK(hipStreamSynchronize(J.s_main));
   op.ready = true;
@@ -536,8 +544,8 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
         w.Xs[2] = (const char *)op.X + (size_t)k * vp3 * es;
         w.xps = op.xps;
       }
-      w.T2 = op.T2; w.In = op.In;
-      w.tps = op.tps; w.ips = op.ips;
+      w.T2 = op.T2; w.In = op.In; w.T2T = op.T2T;
+      w.tps = op.tps; w.ips = op.ips; w.t2tps = op.t2tps; w.lo = op.lo;
       w.W = W; w.o = o; w.vp = vp; w.i = i; w.j = j; w.k = k; w.mt = mt; w.nt = nt;
       EItem &e = ei[pos];
       e.W = W; e.K = J.K.as<double>(); e.t1 = J.t1.as<double>();
@@ -673,7 +681,10 @@ size_t job_footprint(int o, int v, int naux, Prec p) {
   const size_t nX = O * VP * VP * VP, nT2 = O * O * VP * VP, nIn = O * VP * O * O;
   b += 8 * nX;
   if (p == Prec::F32) b += 4 * (nX + nT2 + nIn);
-  if (p == Prec::BF16X3 || p == Prec::BF16X2) b += 6 * (nX + nT2 + nIn);
+  if (p == Prec::BF16X3 || p == Prec::BF16X2) {
+    const size_t LO = (O + 7) / 8 * 8;
+    b += 6 * (nX + nT2 + O * VP * O * LO + O * VP * VP * LO);
+  }
   return b + 32 * 256;
 }
 

@@ -24,8 +24,12 @@ struct WItem {
   const void *Xs[3];  // slices (ix|yf) for x in i, j, k: [vp][vp][vp] each;
                       // part p of slice q at Xs[q] + p * xps
   const void *T2;  // t2,      layout [part][o][o][vp][vp]
-  const void *In;  // -(px|ql), layout [part][o][vp][o][o]
-  size_t xps, tps, ips;   // element stride between BF16 parts
+  const void *In;  // -(px|ql), layout [part][o][vp][o][lo]
+  const void *T2T; // BF16 modes: t2 with the occupied index last,
+                   // [part][o][vp*vp][lo], t2T[p][(y,z)][l] = t2[p][l][y][z]
+  size_t xps, tps, ips, t2tps;   // element stride between BF16 parts
+  int lo;          // length of the occupied rows of In and T2T: o in FP64 and
+                   // FP32 modes, o rounded up to 8 (zero padded) in BF16 modes
   void *W;         // three boxed W arrays of vp^3 each (FP64 or FP32)
   int o, vp, i, j, k;
   int mt, nt;      // tiles along M and N
@@ -84,6 +88,13 @@ hipError_t launch_pad4(const double *src, double *dst, int d0, int d1, int d2, i
 hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_to_bf16_parts(const double *src, uint16_t *dst, size_t n, int nparts,
                                 hipStream_t s);
+// BF16 parts of t2 [o][o][vp][vp] regrouped as [part][o][vp*vp][lo] (occupied
+// index last, zero for l >= o).
+hipError_t launch_t2t_bf16_parts(const double *t2, uint16_t *dst, int o, int vp, int lo,
+                                 int nparts, hipStream_t s);
+// BF16 parts of In [o][vp][o][o] with the last index padded to lo.
+hipError_t launch_in_bf16_parts(const double *in, uint16_t *dst, int o, int vp, int lo,
+                                int nparts, hipStream_t s);
 hipError_t launch_check(const double *x, size_t n, int *flag, hipStream_t s);
 hipError_t launch_mfma_probe(Prec p, void *out, int blocks, int iters, hipStream_t s,
                              double *flops);

@@ -59,9 +59,10 @@ struct DBuf {
 // Operand copies of one precision (FP64 points at the staged arrays).
 struct Operands {
   bool ready = false;
-  const void *X = nullptr, *T2 = nullptr, *In = nullptr;
-  size_t xps = 0, tps = 0, ips = 0;
-  DBuf X_own, T2_own, In_own;
+  const void *X = nullptr, *T2 = nullptr, *In = nullptr, *T2T = nullptr;
+  size_t xps = 0, tps = 0, ips = 0, t2tps = 0;
+  int lo = 0;     // occupied row length of In / T2T
+  DBuf X_own, T2_own, In_own, T2T_own;
 };
 
 struct Job {

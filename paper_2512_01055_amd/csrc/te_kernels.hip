@@ -241,8 +241,6 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
     long nn = okB[u] ? n : 0;
     rowB[u][0] = (((long)su.tq[0] * o + su.tr[0]) * vp + nn) * vp;
     rowB[u][1] = (((long)su.tq[1] * o + su.tr[1]) * vp + nn) * vp;
-    rowI[u][0] = (((long)su.ix[0] * vp + nn) * o + su.iy[0]) * o;
-    rowI[u][1] = (((long)su.ix[1] * vp + nn) * o + su.iy[1]) * o;
   }
   long baseO[2], ksO[2];
 #pragma unroll
@@ -250,9 +248,30 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
     if (su.om[s] == 0) { baseO[s] = (long)su.op[s] * o * vp2; ksO[s] = vp2; }
     else               { baseO[s] = (long)su.op[s] * vp2;     ksO[s] = (long)o * vp2; }
   }
+  // BF16 modes: occupied-segment rows of T2T (t_{p l}^{yz} with l last), read
+  // like the X rows; om = 1 takes the swapped pair (t_{l p}^{yz} = t_{p l}^{zy})
+  const int lo = w.lo;
+  const T *T2T = reinterpret_cast<const T *>(w.T2T);
+  long rowO[TR::SWZ ? CA : 1][2];
+  if constexpr (TR::SWZ) {
+#pragma unroll
+    for (int u = 0; u < CA; ++u) {
+      long mm = okA[u] ? (long)m0 + (tid + u * WG) / CPR : 0;
+      long mx = mm / vp, my = mm - mx * vp;
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        rowO[u][s] = ((long)su.op[s] * vp2 + (su.om[s] ? my * vp + mx : mm)) * lo;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < CB; ++u) {   // In rows have length lo
+    long nn = okB[u] ? (long)n0 + (tid + u * WG) / CPR : 0;
+    rowI[u][0] = (((long)su.ix[0] * vp + nn) * o + su.iy[0]) * lo;
+    rowI[u][1] = (((long)su.ix[1] * vp + nn) * o + su.iy[1]) * lo;
+  }
 
   const int KX = 2 * vp;
-  const int KO = 2 * o;
+  const int KO = TR::SWZ ? 2 * lo : 2 * o;
   const int nkx = (KX + KT - 1) / KT;
   const int nko = (KO + KT - 1) / KT;
   const int ntiles = nkx + nko;
@@ -283,6 +302,31 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
           if (ok) rb[u][p].load(T2 + p * w.tps + off); else rb[u][p].zero();
+        }
+      }
+    } else if constexpr (TR::SWZ) {
+      // occupied segments as 8-element chunks of K-contiguous rows
+      const int kb = (t - nkx) * KT;
+#pragma unroll
+      for (int u = 0; u < CA; ++u) {
+        int kg = kb + kcA[u];
+        bool ok = okA[u] && kg < KO;
+        int seg = kg >= lo;
+        long off = rowO[u][seg] + (kg - seg * lo);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          if (ok) ra[u][p].load(T2T + p * w.t2tps + off); else ra[u][p].zero();
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        int kg = kb + kcB[u];
+        bool ok = okB[u] && kg < KO;
+        int seg = kg >= lo;
+        long off = rowI[u][seg] + (kg - seg * lo);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          if (ok) rb[u][p].load(In + p * w.ips + off); else rb[u][p].zero();
         }
       }
     } else {
@@ -318,7 +362,7 @@ __global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ it
   };
 
   auto store = [&](int t, int buf) {
-    if (t < nkx) {
+    if (t < nkx || TR::SWZ) {
 #pragma unroll
       for (int u = 0; u < CA; ++u) {
         int c = tid + u * WG;
@@ -679,6 +723,41 @@ __global__ void to_bf16_parts_kernel(const double *__restrict__ src, uint16_t *_
   }
 }
 
+__device__ inline void split_store(double r, uint16_t *dst, size_t q, size_t n, int nparts) {
+  for (int p = 0; p < nparts; ++p) {
+    uint16_t h = bf16_rne((float)r);
+    dst[p * n + q] = h;
+    r -= bf16_val(h);
+  }
+}
+
+__global__ void t2t_bf16_kernel(const double *__restrict__ t2, uint16_t *__restrict__ dst, int o,
+                                int vp, int lo, int nparts) {
+  const long vp2 = (long)vp * vp;
+  const size_t n = (size_t)o * vp2 * lo;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const int l = (int)(q % lo);
+    const size_t r = q / lo;
+    const long pair = (long)(r % vp2);
+    const int p = (int)(r / vp2);
+    const double x = l < o ? t2[((long)p * o + l) * vp2 + pair] : 0.0;
+    split_store(x, dst, q, n, nparts);
+  }
+}
+
+__global__ void in_bf16_kernel(const double *__restrict__ in, uint16_t *__restrict__ dst, int o,
+                               int vp, int lo, int nparts) {
+  const size_t n = (size_t)o * vp * o * lo;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const int l = (int)(q % lo);
+    const size_t r = q / lo;                  // (p, x, q') row
+    const double x = l < o ? in[r * o + l] : 0.0;
+    split_store(x, dst, q, n, nparts);
+  }
+}
+
 __global__ void check_kernel(const double *__restrict__ x, size_t n, int *flag) {
   int bad = 0;
   for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
@@ -878,6 +957,20 @@ hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t s)
 hipError_t launch_to_bf16_parts(const double *src, uint16_t *dst, size_t n, int nparts,
                                 hipStream_t s) {
   to_bf16_parts_kernel<<<blocks_for(n), WG, 0, s>>>(src, dst, n, nparts);
+  return hipGetLastError();
+}
+
+hipError_t launch_t2t_bf16_parts(const double *t2, uint16_t *dst, int o, int vp, int lo,
+                                 int nparts, hipStream_t s) {
+  size_t n = (size_t)o * vp * vp * lo;
+  t2t_bf16_kernel<<<blocks_for(n), WG, 0, s>>>(t2, dst, o, vp, lo, nparts);
+  return hipGetLastError();
+}
+
+hipError_t launch_in_bf16_parts(const double *in, uint16_t *dst, int o, int vp, int lo,
+                                int nparts, hipStream_t s) {
+  size_t n = (size_t)o * vp * o * lo;
+  in_bf16_kernel<<<blocks_for(n), WG, 0, s>>>(in, dst, o, vp, lo, nparts);
   return hipGetLastError();
 }
 
