@@ -158,9 +158,11 @@ __device__ inline Setup make_setup(int g, int i, int j, int k) {
 }
 
 // NB: 16-column blocks per tile (BN = 16 NB); WM: 16-row blocks per wave
-// (BM = 4 waves x 16 WM rows).
+// (BM = 4 waves x 16 WM rows). The register budget asks for three waves per
+// SIMD; that is what the two-part BF16 tiles' LDS allows (the other modes are
+// held to two by LDS and are not constrained by it).
 template <Prec P, int NB, int WM>
-__global__ __launch_bounds__(WG) void wbuild_kernel(const WItem *__restrict__ items,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wbuild_kernel(const WItem *__restrict__ items,
                                                     const int *__restrict__ tile_item,
                                                     int tiles_per_item, long total_tiles) {
   using TR = Tr<P>;
