@@ -187,4 +187,5 @@ def make_problem_device(o: int, v: int, naux: int, seed: int, device="cuda:0", *
         t2[i] /= den
     out.t2 = t2
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()     # return the temporaries to the device
     return out
