@@ -20,6 +20,7 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int WG = 256;
 
@@ -29,36 +30,50 @@ template <Prec P> struct Tr;
 // column l%16 and row  (l/16) + 4r  for v_mfma_f64_16x16x4f64  (ROWQ = 1),
 //                      4(l/16) + r  for the FP32 and BF16 forms (ROWQ = 4).
 //
-// LDS rows of FP64/FP32 tiles are padded by one element so that the 16 rows a
-// fragment read touches fall in distinct banks. BF16 tiles (32 elements =
-// four 16-byte chunks per row) are unpadded and instead store chunk c of row
-// r at chunk c ^ ((r >> 2) & 3), which spreads the same reads over all banks
-// and saves the LDS that lets two workgroups share a CU.
+// LDS tiles are unpadded rows of KT elements. The 16-byte chunks of a row are
+// XOR-swizzled: chunk c of row r is stored at chunk c ^ ((r / RP) % CR), with
+// RP rows per 256 bytes (64 banks) and CR chunks per row. The 16 rows one
+// fragment read touches then fall in 16 distinct bank groups, and no padding
+// is spent, which is what lets two (BF16x3, FP64) or three (FP32, BF16x2)
+// workgroups share a CU.
 template <> struct Tr<Prec::F64> {
   using T = double; using Acc = d4; using Out = double;
-  static constexpr int KT = 16, PAD = 1, NP = 1, KM = 4, ROWQ = 1;
-  static constexpr bool SWZ = false;
+  static constexpr int KT = 16, PAD = 0, NP = 1, KM = 4, ROWQ = 1;
+  static constexpr bool SPLIT = false;
 };
 template <> struct Tr<Prec::F32> {
   using T = float; using Acc = f4; using Out = float;
-  static constexpr int KT = 32, PAD = 1, NP = 1, KM = 4, ROWQ = 4;
-  static constexpr bool SWZ = false;
+  static constexpr int KT = 32, PAD = 0, NP = 1, KM = 4, ROWQ = 4;
+  static constexpr bool SPLIT = false;
 };
 template <> struct Tr<Prec::BF16X3> {
   using T = uint16_t; using Acc = f4; using Out = float;
   static constexpr int KT = 32, PAD = 0, NP = 3, KM = 32, ROWQ = 4;
-  static constexpr bool SWZ = true;
+  static constexpr bool SPLIT = true;
 };
 template <> struct Tr<Prec::BF16X2> {
   using T = uint16_t; using Acc = f4; using Out = float;
   static constexpr int KT = 32, PAD = 0, NP = 2, KM = 32, ROWQ = 4;
-  static constexpr bool SWZ = true;
+  static constexpr bool SPLIT = true;
 };
 
-// Column of element k of LDS row r (see the layout note above).
+template <typename TR> struct Swz {
+  static constexpr int EC = 16 / sizeof(typename TR::T);            // elements per chunk
+  static constexpr int CR = TR::KT / EC;                             // chunks per row
+  static constexpr int RP = 256 / (TR::KT * (int)sizeof(typename TR::T));  // rows per 256 B
+};
+// Column of element k of LDS row r.
 template <typename TR> __device__ inline int lcol(int r, int k) {
-  if constexpr (TR::SWZ) return (((k >> 3) ^ ((r >> 2) & 3)) << 3) | (k & 7);
-  else return k;
+  using S = Swz<TR>;
+  return ((((k / S::EC) ^ ((r / S::RP) % S::CR))) * S::EC) | (k % S::EC);
+}
+// Store eight consecutive elements (k0 % 8 == 0) of row r as swizzled chunks.
+template <typename TR, typename T, typename CH>
+__device__ inline void store_chunk(T *row, int r, int k0, const CH &c) {
+  using S = Swz<TR>;
+#pragma unroll
+  for (int q = 0; q < CH::NQ; ++q)
+    *reinterpret_cast<u32x4 *>(row + lcol<TR>(r, k0 + q * S::EC)) = c.q[q];
 }
 
 // Global-address-space views. Operand pointers reach the kernels through
@@ -69,8 +84,6 @@ template <typename T> using gptr = const __attribute__((address_space(1))) T *;
 template <typename T> using gptr_w = __attribute__((address_space(1))) T *;
 template <typename T> __device__ inline T gld(const T *p) { return *(gptr<T>)(p); }
 template <typename T> __device__ inline void gst(T *p, T x) { *(gptr_w<T>)(p) = x; }
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Eight consecutive elements, moved as 16-byte words.
 template <typename T> struct Chunk {
@@ -254,8 +267,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
   // like the X rows; om = 1 takes the swapped pair (t_{l p}^{yz} = t_{p l}^{zy})
   const int lo = w.lo;
   const T *T2T = reinterpret_cast<const T *>(w.T2T);
-  long rowO[TR::SWZ ? CA : 1][2];
-  if constexpr (TR::SWZ) {
+  long rowO[TR::SPLIT ? CA : 1][2];
+  if constexpr (TR::SPLIT) {
 #pragma unroll
     for (int u = 0; u < CA; ++u) {
       long mm = okA[u] ? (long)m0 + (tid + u * WG) / CPR : 0;
@@ -273,7 +286,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
   }
 
   const int KX = 2 * vp;
-  const int KO = TR::SWZ ? 2 * lo : 2 * o;
+  const int KO = TR::SPLIT ? 2 * lo : 2 * o;
   const int nkx = (KX + KT - 1) / KT;
   const int nko = (KO + KT - 1) / KT;
   const int ntiles = nkx + nko;
@@ -306,7 +319,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
           if (ok) rb[u][p].load(T2 + p * w.tps + off); else rb[u][p].zero();
         }
       }
-    } else if constexpr (TR::SWZ) {
+    } else if constexpr (TR::SPLIT) {
       // occupied segments as 8-element chunks of K-contiguous rows
       const int kb = (t - nkx) * KT;
 #pragma unroll
@@ -364,21 +377,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
   };
 
   auto store = [&](int t, int buf) {
-    if (t < nkx || TR::SWZ) {
+    if (t < nkx || TR::SPLIT) {
 #pragma unroll
       for (int u = 0; u < CA; ++u) {
         int c = tid + u * WG;
         if (c < BM * CPR) {
           int row = c / CPR;
 #pragma unroll
-          for (int p = 0; p < NP; ++p) {
-            if constexpr (TR::PAD % 8 == 0) {
-              *reinterpret_cast<Chunk<T> *>(&As[buf][p][row][lcol<TR>(row, kcA[u])]) = ra[u][p];
-            } else {
-#pragma unroll
-              for (int e = 0; e < 8; ++e) As[buf][p][row][kcA[u] + e] = ra[u][p].get(e);
-            }
-          }
+          for (int p = 0; p < NP; ++p) store_chunk<TR>(&As[buf][p][row][0], row, kcA[u], ra[u][p]);
         }
       }
     } else {
@@ -401,14 +407,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
       if (c < BN * CPR) {
         int row = c / CPR;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          if constexpr (TR::PAD % 8 == 0) {
-            *reinterpret_cast<Chunk<T> *>(&Bs[buf][p][row][lcol<TR>(row, kcB[u])]) = rb[u][p];
-          } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) Bs[buf][p][row][kcB[u] + e] = rb[u][p].get(e);
-          }
-        }
+        for (int p = 0; p < NP; ++p) store_chunk<TR>(&Bs[buf][p][row][0], row, kcB[u], rb[u][p]);
       }
     }
   };
@@ -437,9 +436,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
         using E = T;
         E av[WM], bv[NB];
 #pragma unroll
-        for (int rb_ = 0; rb_ < WM; ++rb_) av[rb_] = As[cur][0][wrow + rb_ * 16 + fr][kk * 4 + fk];
+        for (int rb_ = 0; rb_ < WM; ++rb_) {
+          const int r = wrow + rb_ * 16 + fr;
+          av[rb_] = As[cur][0][r][lcol<TR>(r, kk * 4 + fk)];
+        }
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) bv[cb] = Bs[cur][0][cb * 16 + fr][kk * 4 + fk];
+        for (int cb = 0; cb < NB; ++cb) bv[cb] = Bs[cur][0][cb * 16 + fr][lcol<TR>(cb * 16 + fr, kk * 4 + fk)];
 #pragma unroll
         for (int rb_ = 0; rb_ < WM; ++rb_)
 #pragma unroll
