@@ -33,13 +33,21 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+def wbuild_source_hash() -> str:
+    """First 16 hex digits of the SHA-256 over the W-build sources (shared
+    device header, then the kernel file)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("te_device.h", "te_wbuild.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2512_01055_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source has changed since the counters were taken."""
     import glob
-    import hashlib
-    src = os.path.join(ROOT, "paper_2512_01055_amd", "csrc", "te_kernels.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = wbuild_source_hash()
     for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
         for line in open(path):
             if line.startswith("traffic_bytes_per_launch:"):
