@@ -80,7 +80,9 @@ typedef struct te_problem {
 typedef enum te_xmode {
   TE_X_AUTO = 0,        /* materialise all o*v^3 when it fits, else on the fly */
   TE_X_RESIDENT = 1,    /* materialise all slices at te_init                   */
-  TE_X_ON_THE_FLY = 2   /* assemble slices from B_ov, B_vv into a slice cache  */
+  TE_X_ON_THE_FLY = 2   /* assemble slices from B_ov, B_vv into a slice cache;
+                           the (ov|ov) blocks of Eq. 3 are then assembled per
+                           triple instead of held as an o^2 v^2 array           */
 } te_xmode;
 
 typedef struct te_config {
@@ -98,15 +100,18 @@ typedef struct te_stats {
   double tflops;         /* flops / seconds / 1e12                               */
   int64_t n_triples;     /* occupied triples evaluated                           */
   double stage_seconds;  /* part of `seconds` spent preparing operands           */
-  double assemble_flops; /* on-the-fly mode: flops spent assembling slices       */
+  double assemble_flops; /* on-the-fly mode: flops spent assembling (vv|vo)
+                            slices and per-triple (ov|ov) blocks               */
   /* Device time of the kernels, from HIP events recorded around each launch
    * on the stream it runs on: the W build (MFMA) and the energy consumer. */
   double w_kernel_seconds;
   int64_t w_launches;
   double e_kernel_seconds;
   int64_t e_launches;
-  /* On-the-fly (vv|vo) mode: slices assembled, their device time, and the
-   * number of slices the cache held. */
+  /* On-the-fly (vv|vo) mode: slices assembled, their device time (on the W
+   * stream, ahead of the W builds that read them), and the number of slices
+   * the cache held. The per-triple (ov|ov) blocks run on the energy stream,
+   * overlapped with the W build, and are not part of assemble_seconds. */
   int64_t slices_assembled;
   double assemble_seconds;
   int64_t cache_slices;
@@ -127,7 +132,10 @@ te_status te_init(const te_problem *prob, const te_config *cfg, te_job *out);
 /* Evaluate E(T) over all occupied triples i<=j<=k (i=j=k contribute zero and
  * are skipped). Blocks until done. `per_triple` (host, optional) receives
  * the weighted partial of each triple in the order of te_triple_list.
- * The result is bitwise reproducible for a given problem and precision. */
+ * The result is bitwise reproducible for a given problem and precision.
+ * The first call in a reduced precision converts the operands and keeps the
+ * copy for later calls; a call in the other reduced precision (FP32 versus
+ * the BF16 modes) releases it first, so a job holds at most one such copy. */
 te_status te_energy(te_job job, te_precision prec, double *e_t, double *per_triple,
                     te_stats *st);
 

@@ -231,11 +231,14 @@ static void stage(Job &J, const te_problem &P) {
     J.Bov = device_view(J, P.B_ov, (size_t)naux * o * v, J.Bov_own);
     J.Boo = device_view(J, P.B_oo, (size_t)naux * o * o, J.Boo_own);
     J.Bvv = device_view(J, P.B_vv, (size_t)naux * v * v, J.Bvv_own);
-    // K[p][x][q][y] = (px|qy), for V (Eq. 3)
-    jalloc(J, J.K, (size_t)o * vp * o * vp * 8);
-    HIPCHK(hipMemsetAsync(J.K.p, 0, J.K.bytes, s));
-    gemm_stage(J, J.Bov, (long)o * v, J.Bov, (long)o * v, o * v, o * v, naux, v,
-               (long)vp * o * vp, (long)o * vp, v, vp, 1, 1.0, J.K.as<double>());
+    // K[p][x][q][y] = (px|qy), for V (Eq. 3); when (vv|vo) is assembled on
+    // the fly the three blocks a triple reads are assembled with it instead
+    if (J.x_resident) {
+      jalloc(J, J.K, (size_t)o * vp * o * vp * 8);
+      HIPCHK(hipMemsetAsync(J.K.p, 0, J.K.bytes, s));
+      gemm_stage(J, J.Bov, (long)o * v, J.Bov, (long)o * v, o * v, o * v, naux, v,
+                 (long)vp * o * vp, (long)o * vp, v, vp, 1, 1.0, J.K.as<double>());
+    }
     // In[p][x][q][l] = -(px|ql), the occupied term of Eq. 2 with its sign
     jalloc(J, J.In, (size_t)o * vp * o * o * 8);
     HIPCHK(hipMemsetAsync(J.In.p, 0, J.In.bytes, s));
@@ -288,10 +291,25 @@ static void validate_device(Job &J, const te_problem &P) {
 }
 
 // ------------------------------------------------------------ precisions
+static void drop_operands(Operands &op) {
+  op.X_own.release(); op.T2_own.release(); op.In_own.release(); op.T2T_own.release();
+  op.ready = false;
+  op.X = op.T2 = op.In = op.T2T = nullptr;
+  op.xps = op.tps = op.ips = op.t2tps = 0;
+  op.lo = 0;
+}
+
 const Operands &ensure_prec(Job &J, Prec p) {
   int slot = (p == Prec::BF16X2) ? (int)Prec::BF16X3 : (int)p;
   Operands &op = J.op[slot];
   if (op.ready) return op;
+  // at most one reduced-precision copy at a time: it is rebuilt from the
+  // FP64 arrays in milliseconds, and the HBM goes to the slice cache
+  if (p != Prec::F64) {
+    HIPCHK(hipStreamSynchronize(J.s_main));
+    if (J.s_aux) HIPCHK(hipStreamSynchronize(J.s_aux));
+    drop_operands(J.op[slot == (int)Prec::F32 ? (int)Prec::BF16X3 : (int)Prec::F32]);
+  }
   const int o = J.o, vp = J.vp;
   const size_t nT2 = (size_t)o * o * vp * vp;
   const size_t nIn = (size_t)o * vp * o * o;
@@ -405,8 +423,10 @@ static Plan plan_resident(long ntr, int B) {
 // Occupied indices are grouped in blocks of S/3; triples run block-triple by
 // block-triple so that a cache of S slices is refilled about once per block
 // change. Within a batch every needed slice is resident; misses evict the
-// least recently used slice not needed by the batch.
-static Plan plan_on_the_fly(const int *ijk, long ntr, int B, int S) {
+// least recently used slice not needed by the batch. `held` gives the slot
+// contents on entry (-1: empty) and receives them on return.
+static Plan plan_on_the_fly(const int *ijk, long ntr, int B, std::vector<int> &held) {
+  const int S = (int)held.size();
   Plan P;
   const int bs = std::max(1, S / 3);
   P.order.resize(ntr);
@@ -419,9 +439,10 @@ static Plan plan_on_the_fly(const int *ijk, long ntr, int B, int S) {
       if (x[d] != y[d]) return x[d] < y[d];
     return false;
   });
-  std::vector<int> held(S, -1);        // slot -> occupied index
   std::vector<long> last(S, -1);       // slot -> last batch that used it
   std::map<int, int> where;            // occupied index -> slot
+  for (int q = 0; q < S; ++q)
+    if (held[q] >= 0) where[held[q]] = q;
   P.slot.resize(ntr);
   long pos = 0, bno = 0;
   while (pos < ntr) {
@@ -482,9 +503,33 @@ static void assemble_slice(Job &J, Prec p, int occ, void *slot, double *tmp64, h
     HIPCHK(launch_to_bf16_parts(tmp64, (uint16_t *)slot, n, 3, s));
 }
 
+void resident_k_views(const Job &J, int i, int j, int k, EItem &e) {
+  const long o = J.o, vp = J.vp;
+  const double *K = J.K.as<double>();
+  e.Kjk = K + (j * vp * o + k) * vp;
+  e.Kik = K + (i * vp * o + k) * vp;
+  e.Kij = K + (i * vp * o + j) * vp;
+  e.kld = o * vp;
+}
+
+// (px|qy) for one occupied pair as a v x v block with row stride vp (Eq. 6
+// with two (ov) factors), on stream s.
+static void assemble_k_block(Job &J, int p, int q, double *dst, hipStream_t s) {
+  const int o = J.o, v = J.v, vp = J.vp;
+  GemmTN g{J.Bov + (long)p * v, J.Bov + (long)q * v, dst, v, v, J.naux, (long)o * v,
+           (long)o * v, v, 0, vp, v, 0, 1, 1.0};
+  HIPCHK(launch_gemm_tn(g, s));
+}
+
 void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double *per_triple,
                  te_stats *st) {
   auto t0 = std::chrono::steady_clock::now();
+  const int pslot = (p == Prec::BF16X2) ? (int)Prec::BF16X3 : (int)p;
+  if (J.xc.pslot >= 0 && J.xc.pslot != pslot) {   // slices of another precision
+    HIPCHK(hipStreamSynchronize(J.s_main));
+    if (J.s_aux) HIPCHK(hipStreamSynchronize(J.s_aux));
+    J.xc.release();
+  }
   const Operands &op = ensure_prec(J, p);
   auto t1 = std::chrono::steady_clock::now();
   const bool fly = !J.x_resident;
@@ -500,26 +545,50 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
   const size_t osz = out_size(p);
   const size_t es = elem_size(p);
 
-  // scratch: W for two batches, partials for two batches, per-triple results
-  DBuf wbuf, part, eout, esum, witems, eitems, ritems, cache, tmp64;
-  wbuf.alloc(2 * (size_t)B * 3 * vp3 * osz, &J.used, J.budget);
-  part.alloc(2 * (size_t)B * J.nsext * 8, &J.used, J.budget);
-  eout.alloc((size_t)ntr * 8, &J.used, J.budget);
-  esum.alloc(8, &J.used, J.budget);
+  // scratch: W for two batches, partials for two batches, per-triple results,
+  // and (on the fly) three (ov|ov) blocks per triple of the two batches
+  DBuf wbuf, part, eout, esum, witems, eitems, ritems, kbuf;
+  const size_t kblk = (size_t)vp * vp;
+  auto scratch = [&] {
+    wbuf.alloc(2 * (size_t)B * 3 * vp3 * osz, &J.used, J.budget);
+    part.alloc(2 * (size_t)B * J.nsext * 8, &J.used, J.budget);
+    eout.alloc((size_t)ntr * 8, &J.used, J.budget);
+    esum.alloc(8, &J.used, J.budget);
+    if (fly) kbuf.alloc(2 * (size_t)B * 3 * kblk * 8, &J.used, J.budget);
+  };
+  try {
+    scratch();
+  } catch (const Fail &f) {
+    if (f.s != TE_ENOMEM || !J.xc.mem.p) throw;
+    wbuf.release(); part.release(); eout.release(); esum.release(); kbuf.release();
+    J.xc.release();                  // a kept cache gives way to this call's scratch
+    scratch();
+  }
 
   Plan P;
   size_t slot_bytes = 0;
+  std::vector<int> after;   // slot contents once this call completes
   if (fly) {
     slot_bytes = vp3 * es * (size_t)nparts(p);
-    if (p != Prec::F64) tmp64.alloc(vp3 * 8, &J.used, J.budget);
-    long room = (long)((J.budget - std::min(J.budget, J.used + ((size_t)1 << 28))) / slot_bytes);
-    int S = J.x_cache ? J.x_cache : (int)std::min<long>(room, o);
-    S = std::min(S, o);
-    if (S < 3 || S > room)
-      throw Fail(TE_ENOMEM, "no room for three (vv|vo) slices of " + std::to_string(slot_bytes) +
-                                " bytes in the HBM budget");
-    cache.alloc((size_t)S * slot_bytes, &J.used, J.budget);
-    P = plan_on_the_fly(ijk, ntr, B, S);
+    if (!J.xc.mem.p) {
+      if (p != Prec::F64) J.xc.tmp64.alloc(vp3 * 8, &J.used, J.budget);
+      long room = (long)((J.budget - std::min(J.budget, J.used + ((size_t)1 << 28))) / slot_bytes);
+      int S = J.x_cache ? J.x_cache : (int)std::min<long>(room, o);
+      S = std::min(S, o);
+      if (S < 3 || S > room) {
+        J.xc.release();
+        throw Fail(TE_ENOMEM, "no room for three (vv|vo) slices of " +
+                                  std::to_string(slot_bytes) + " bytes in the HBM budget");
+      }
+      J.xc.mem.alloc((size_t)S * slot_bytes, &J.used, J.budget);
+      J.xc.S = S;
+      J.xc.slot_bytes = slot_bytes;
+      J.xc.pslot = pslot;
+      J.xc.held.assign(S, -1);
+    }
+    after = J.xc.held;
+    P = plan_on_the_fly(ijk, ntr, B, after);
+    J.xc.held.assign(J.xc.S, -1);   // unknown until this call completes
   } else {
     P = plan_resident(ntr, B);
   }
@@ -536,7 +605,8 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
       void *W = wbuf.as<char>() + ((size_t)sl * B + q) * 3 * vp3 * osz;
       WItem &w = wi[pos];
       if (fly) {
-        for (int d = 0; d < 3; ++d) w.Xs[d] = cache.as<char>() + (size_t)P.slot[pos][d] * slot_bytes;
+        for (int d = 0; d < 3; ++d)
+          w.Xs[d] = J.xc.mem.as<char>() + (size_t)P.slot[pos][d] * slot_bytes;
         w.xps = vp3;
       } else {
         w.Xs[0] = (const char *)op.X + (size_t)i * vp3 * es;
@@ -548,7 +618,13 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
       w.tps = op.tps; w.ips = op.ips; w.t2tps = op.t2tps; w.lo = op.lo;
       w.W = W; w.o = o; w.vp = vp; w.i = i; w.j = j; w.k = k; w.mt = mt; w.nt = nt;
       EItem &e = ei[pos];
-      e.W = W; e.K = J.K.as<double>(); e.t1 = J.t1.as<double>();
+      if (fly) {
+        const double *kb = kbuf.as<double>() + ((size_t)sl * B + q) * 3 * kblk;
+        e.Kjk = kb; e.Kik = kb + kblk; e.Kij = kb + 2 * kblk; e.kld = vp;
+      } else {
+        resident_k_views(J, i, j, k, e);
+      }
+      e.W = W; e.t1 = J.t1.as<double>();
       e.eo = J.eo.as<double>(); e.ev = J.ev.as<double>(); e.sext = J.sext.as<int>();
       e.part = part.as<double>() + ((size_t)sl * B + q) * J.nsext;
       e.o = o; e.v = J.v; e.vp = vp; e.nT = vp / BOX; e.i = i; e.j = j; e.k = k;
@@ -579,14 +655,27 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
     // W build (which may still read the slot being refilled)
     if (fly) HIPCHK(hipEventRecord(ta.start[b], J.s_aux));
     for (auto &ld : P.loads[b])
-      assemble_slice(J, p, ld.first, cache.as<char>() + (size_t)ld.second * slot_bytes,
-                     tmp64.as<double>(), J.s_aux);
+      assemble_slice(J, p, ld.first, J.xc.mem.as<char>() + (size_t)ld.second * slot_bytes,
+                     J.xc.tmp64.as<double>(), J.s_aux);
     if (fly) HIPCHK(hipEventRecord(ta.stop[b], J.s_aux));
     HIPCHK(hipEventRecord(tw.start[b], J.s_aux));
     HIPCHK(launch_wbuild(p, witems.as<WItem>() + first, nullptr, cnt, tiles, (long)cnt * tiles,
                          wc, J.s_aux));
     HIPCHK(hipEventRecord(tw.stop[b], J.s_aux));
     HIPCHK(hipEventRecord(J.ev_w[slot], J.s_aux));
+    // the batch's (ov|ov) blocks, on the energy stream while W is built (the
+    // energy launch two batches back, the last reader of these blocks, is
+    // earlier on the same stream)
+    if (fly) {
+      for (int q = 0; q < cnt; ++q) {
+        const long t = P.order[first + q];
+        const int i = ijk[3 * t], j = ijk[3 * t + 1], k = ijk[3 * t + 2];
+        double *kb = kbuf.as<double>() + ((size_t)slot * B + q) * 3 * kblk;
+        assemble_k_block(J, j, k, kb, J.s_main);
+        assemble_k_block(J, i, k, kb + kblk, J.s_main);
+        assemble_k_block(J, i, j, kb + 2 * kblk, J.s_main);
+      }
+    }
     HIPCHK(hipStreamWaitEvent(J.s_main, J.ev_w[slot], 0));
     HIPCHK(hipEventRecord(te_.start[b], J.s_main));
     HIPCHK(launch_energy(f64, eitems.as<EItem>() + first, nullptr, cnt, J.nsext,
@@ -601,6 +690,7 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
   if (per_triple)
     HIPCHK(hipMemcpyAsync(per_triple, eout.p, ntr * 8, hipMemcpyDeviceToHost, J.s_main));
   HIPCHK(hipStreamSynchronize(J.s_main));
+  if (fly) J.xc.held = after;
   auto t2 = std::chrono::steady_clock::now();
   if (e_sum) *e_sum = E;
   if (st) {
@@ -609,20 +699,22 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
     st->n_triples = ntr;
     st->flops = (double)ntr * flops_per_triple(o, J.v);
     st->tflops = st->flops / std::max(st->seconds, 1e-12) / 1e12;
-    st->assemble_flops = (double)P.nloads * 2.0 * J.naux * (double)J.v * J.v * J.v;
+    st->assemble_flops = (double)P.nloads * 2.0 * J.naux * (double)J.v * J.v * J.v
+                       + (fly ? (double)ntr * 3 * 2.0 * J.naux * (double)J.v * J.v : 0.0);
     st->w_kernel_seconds = tw.total();
     st->w_launches = nbatch;
     st->e_kernel_seconds = te_.total();
     st->e_launches = nbatch;
     st->slices_assembled = P.nloads;
     st->assemble_seconds = fly ? ta.total() : 0.0;
-    st->cache_slices = fly ? (int64_t)(cache.bytes / std::max<size_t>(slot_bytes, 1)) : 0;
+    st->cache_slices = fly ? J.xc.S : 0;
   }
 }
 
 int64_t plan_slice_loads(int o, int S, int B) {
   std::vector<int> t = triple_list_host(o);
-  Plan P = plan_on_the_fly(t.data(), (long)t.size() / 3, B, S);
+  std::vector<int> held(S, -1);
+  Plan P = plan_on_the_fly(t.data(), (long)t.size() / 3, B, held);
   return P.nloads;
 }
 

@@ -11,6 +11,7 @@ namespace te {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -25,10 +26,19 @@ template <Prec P> struct Tr;
 //
 // LDS tiles are unpadded rows of KT elements. The 16-byte chunks of a row are
 // XOR-swizzled: chunk c of row r is stored at chunk c ^ ((r / RP) % CR), with
-// RP rows per 256 bytes (64 banks) and CR chunks per row. The 16 rows one
-// fragment read touches then fall in 16 distinct bank groups, and no padding
-// is spent, which is what lets two (BF16x3, FP64) or three (FP32, BF16x2)
-// workgroups share a CU.
+// CR chunks per row. No padding is spent, which is what lets two (BF16x3,
+// FP64) or three (FP32, BF16x2) workgroups share a CU.
+//
+// The LDS serves 128 bytes per clock (32 banks of 4 bytes: the W build's
+// bank-conflict counter matches this model and not a 64-bank one), so a
+// 16-byte-per-lane access runs in groups of 8 lanes. For the BF16 tiles (64
+// bytes per row) RP is 2 rows: the 8 lanes of a fragment read take one chunk
+// of 8 consecutive rows, which the swizzle puts in 8 distinct bank groups,
+// and the chunk stores of a group cover whole rows: both conflict-free. The
+// FP64 and FP32 fragments are one element per lane (16 rows at one k per
+// 128 bytes, necessarily 2-way on 32 banks); there RP is 2 rows per 256
+// bytes, which measured faster than conflict-free 16-byte reads that feed
+// two or four k steps at once.
 template <> struct Tr<Prec::F64> {
   using T = double; using Acc = d4; using Out = double;
   static constexpr int KT = 16, PAD = 0, NP = 1, KM = 4, ROWQ = 1;
@@ -53,7 +63,7 @@ template <> struct Tr<Prec::BF16X2> {
 template <typename TR> struct Swz {
   static constexpr int EC = 16 / sizeof(typename TR::T);            // elements per chunk
   static constexpr int CR = TR::KT / EC;                             // chunks per row
-  static constexpr int RP = 256 / (TR::KT * (int)sizeof(typename TR::T));  // rows per 256 B
+  static constexpr int RP = (TR::SPLIT ? 128 : 256) / (TR::KT * (int)sizeof(typename TR::T));
 };
 // Column of element k of LDS row r.
 template <typename TR> __device__ inline int lcol(int r, int k) {

@@ -38,7 +38,11 @@ struct WItem {
 // One occupied triple's energy: sum over virtual box sextets.
 struct EItem {
   const void *W;       // as written by the W build
-  const double *K;     // (px|qy), layout [o][vp][o][vp]
+  // (jb|kc), (ia|kc), (ia|jb) for this triple, each a v x v block with row
+  // stride kld (views of the resident [o][vp][o][vp] array, or per-triple
+  // blocks assembled from the factors)
+  const double *Kjk, *Kik, *Kij;
+  long kld;
   const double *t1;    // [o][vp]
   const double *eo;    // [o]
   const double *ev;    // [vp]

@@ -83,6 +83,17 @@ struct Job {
   DBuf Bov_own, Boo_own, Bvv_own;
   const double *Bov = nullptr, *Boo = nullptr, *Bvv = nullptr;
   Operands op[4];
+  // On-the-fly mode: the (vv|vo) slice cache and which occupied index each
+  // slot holds (-1: empty), kept across calls in one precision so that a job
+  // evaluated in pieces does not start from a cold cache.
+  struct SliceCache {
+    int pslot = -1;               // operand slot (precision) of the slices
+    int S = 0;
+    size_t slot_bytes = 0;
+    DBuf mem, tmp64;
+    std::vector<int> held;
+    void release() { mem.release(); tmp64.release(); held.clear(); S = 0; pslot = -1; }
+  } xc;
   int nT = 0, nsext = 0;
   ~Job();
 };
@@ -101,6 +112,7 @@ void jalloc(Job &J, DBuf &b, size_t n);
 size_t job_footprint(int o, int v, int naux, Prec p);
 int out_bytes(Prec p);
 const Operands &ensure_prec(Job &J, Prec p);
+void resident_k_views(const Job &J, int i, int j, int k, EItem &e);
 void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double *per_triple,
                  te_stats *st);
 std::vector<int> triple_list_host(int o);

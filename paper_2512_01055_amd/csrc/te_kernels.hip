@@ -47,7 +47,7 @@ __global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ it
     local = bid - (long)it * blks_per_item;
   }
   const EItem &e = items[it];
-  const int o = e.o, v = e.v, vp = e.vp, nT = e.nT;
+  const int v = e.v, vp = e.vp, nT = e.nT;
   const int i = e.i, j = e.j, k = e.k;
   const int packed = e.sext[local];
   int T[3] = {packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023};
@@ -97,9 +97,9 @@ __global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ it
                          - 2.0 * box[sd + bxi(x0, x2, x1)] - 2.0 * box[se + bxi(x1, x0, x2)]
                          - 2.0 * box[sf + bxi(x2, x1, x0)];
         // singles term (Eq. 3): t_i^a (jb|kc) + t_j^b (ia|kc) + t_k^c (ia|jb)
-        const double vt = gld(t1i + a) * gld(e.K + (((long)j * vp + b) * o + k) * vp + c)
-                        + gld(t1j + b) * gld(e.K + (((long)i * vp + a) * o + k) * vp + c)
-                        + gld(t1k + c) * gld(e.K + (((long)i * vp + a) * o + j) * vp + b);
+        const double vt = gld(t1i + a) * gld(e.Kjk + b * e.kld + c)
+                        + gld(t1j + b) * gld(e.Kik + a * e.kld + c)
+                        + gld(t1k + c) * gld(e.Kij + a * e.kld + b);
         const double d = ((eijk - gld(e.ev + a)) - gld(e.ev + b)) - gld(e.ev + c);
         acc += (w0 + vt) * z / d;
       }
@@ -155,8 +155,8 @@ __global__ __launch_bounds__(1024) void sum_kernel(const double *__restrict__ x,
 constexpr int GT = 64, GK = 16;
 
 __global__ __launch_bounds__(WG) void gemm_tn_kernel(GemmTN g) {
-  __shared__ double As[GK][GT];
-  __shared__ double Bs[GK][GT];
+  __shared__ __attribute__((aligned(16))) double As[GK][GT];
+  __shared__ __attribute__((aligned(16))) double Bs[GK][GT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -165,13 +165,22 @@ __global__ __launch_bounds__(WG) void gemm_tn_kernel(GemmTN g) {
     for (int b = 0; b < 2; ++b)
       for (int r = 0; r < 4; ++r) acc[a][b][r] = 0.0;
   for (int k0 = 0; k0 < g.K; k0 += GK) {
+    // a thread moves two consecutive elements of a k row, a wave two whole
+    // rows: coalesced loads and 16-byte LDS stores that fill whole rows
+    // (conflict-free); operands may sit at any 8-byte offset, so the global
+    // loads stay element-wise
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      int e = tid * 4 + u;
-      int q = e / GT, c = e % GT;
+    for (int u = 0; u < 2; ++u) {
+      int e = tid + u * WG;
+      int q = e >> 5, c = (e & 31) * 2;
       int kq = k0 + q;
-      As[q][c] = (kq < g.K && m0 + c < g.M) ? g.A[(long)kq * g.lda + m0 + c] : 0.0;
-      Bs[q][c] = (kq < g.K && n0 + c < g.N) ? g.B[(long)kq * g.ldb + n0 + c] : 0.0;
+      d2 a2, b2;
+      a2[0] = (kq < g.K && m0 + c < g.M) ? g.A[(long)kq * g.lda + m0 + c] : 0.0;
+      a2[1] = (kq < g.K && m0 + c + 1 < g.M) ? g.A[(long)kq * g.lda + m0 + c + 1] : 0.0;
+      b2[0] = (kq < g.K && n0 + c < g.N) ? g.B[(long)kq * g.ldb + n0 + c] : 0.0;
+      b2[1] = (kq < g.K && n0 + c + 1 < g.N) ? g.B[(long)kq * g.ldb + n0 + c + 1] : 0.0;
+      *reinterpret_cast<d2 *>(&As[q][c]) = a2;
+      *reinterpret_cast<d2 *>(&Bs[q][c]) = b2;
     }
     __syncthreads();
 #pragma unroll

@@ -326,7 +326,7 @@ ServerImpl::Launch ServerImpl::launch_round() {
     const long nt_ = 3L * w.mt * w.nt;
     for (long x = 0; x < nt_; ++x) S.h_tmap[t0 + x] = q;
     EItem &e = S.h_ei[q];
-    e.W = W; e.K = J.K.as<double>(); e.t1 = J.t1.as<double>();
+    e.W = W; resident_k_views(J, i, jj, k, e); e.t1 = J.t1.as<double>();
     e.eo = J.eo.as<double>(); e.ev = J.ev.as<double>(); e.sext = J.sext.as<int>();
     e.part = S.part.as<double>() + b0;
     e.o = J.o; e.v = J.v; e.vp = (int)vp; e.nT = (int)(vp / BOX);

@@ -69,7 +69,6 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
   constexpr int CPR = KT / 8;                     // 8-element chunks per row
   constexpr int CA = (BM * KT / 8 + WG - 1) / WG; // A chunks per thread
   constexpr int CB = (BN * KT / 8 + WG - 1) / WG; // B chunks per thread
-  constexpr int CAO = BM / 8;                     // O-phase A: chunks per k row
 
   __shared__ __attribute__((aligned(16))) T As[2][NP][BM][LD];
   __shared__ __attribute__((aligned(16))) T Bs[2][NP][BN][LD];
@@ -226,12 +225,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
         }
       }
     } else {
+      // K-major A: thread c takes k = c % KT and eight consecutive m, so the
+      // transposed LDS stores of a lane group fill one row (conflict-free)
       const int kb = (t - nkx) * KT;
 #pragma unroll
       for (int u = 0; u < CA; ++u) {
         int c = tid + u * WG;
-        int kk = c / CAO;
-        int mc = (c % CAO) * 8;
+        int kk = c % KT;
+        int mc = (c / KT) * 8;
         int kg = kb + kk;
         long m = m0 + mc;
         bool ok = (c < BM * CPR) && kg < KO && m < M;
@@ -273,8 +274,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
       for (int u = 0; u < CA; ++u) {
         int c = tid + u * WG;
         if (c < BM * CPR) {
-          int kk = c / CAO;
-          int mc = (c % CAO) * 8;
+          int kk = c % KT;
+          int mc = (c / KT) * 8;
 #pragma unroll
           for (int p = 0; p < NP; ++p)
 #pragma unroll

@@ -262,3 +262,43 @@ def test_huge_sampled_triples_on_the_fly():
             print(f"per-triple rel max {rel.max():.3e}, cache {st['cache_slices']} slices")
             assert np.all(rel <= (1e-11 if prec == "fp64" else TOL[prec]))
     del P
+
+
+def test_precision_switch_rebuilds_reduced_copies():
+    """A job keeps one reduced-precision operand copy at a time: switching
+    FP32 -> BF16 -> FP32 rebuilds the FP32 copy, with unchanged results."""
+    P = make_problem(5, 40, 30, 29)
+    te = _te()
+    with te.Job(P, device=0) as job:
+        E32a, _, pa = job.energy("fp32", per_triple=True)
+        E16, _, _ = job.energy("bf16x2", per_triple=True)
+        E16b, _, _ = job.energy("bf16x3", per_triple=True)
+        E32b, _, pb = job.energy("fp32", per_triple=True)
+        E64, _ = job.energy("fp64")
+    assert E32a == E32b and np.array_equal(pa, pb)
+    for E in (E32a, E16, E16b):
+        assert abs(E - E64) <= 1e-6 * abs(E64)
+
+
+def test_slice_cache_kept_across_calls():
+    """On the fly, the slice cache outlives a call: repeating a call that
+    fits the cache assembles nothing, and evaluating a job in pieces, or
+    after a change of precision, still gives the resident values bitwise."""
+    te = _te()
+    P = make_problem(9, 48, 40, 28)
+    ref = {}
+    with te.Job(P, device=0, x_mode="resident") as job:
+        for prec in ("fp64", "bf16x3"):
+            ref[prec] = job.energy(prec, per_triple=True)[2]
+    allt = te.triple_list(P.o)
+    sub = allt[allt[:, 2] < 6]                 # occupied indices 0..5 only
+    idx = np.nonzero(allt[:, 2] < 6)[0]
+    with te.Job(P, device=0, x_mode="on_the_fly", x_cache_slices=7) as job:
+        _, p1, st1 = job.energy_triples(sub, "fp64")
+        _, p2, st2 = job.energy_triples(sub, "fp64")
+        assert st1["slices_assembled"] == 6 and st2["slices_assembled"] == 0
+        assert np.array_equal(p1, p2) and np.array_equal(p1, ref["fp64"][idx])
+        pieces = [job.energy_triples(allt[q:q + 40], "fp64")[1] for q in range(0, len(allt), 40)]
+        assert np.array_equal(np.concatenate(pieces), ref["fp64"])
+        assert np.array_equal(job.energy("bf16x3", per_triple=True)[2], ref["bf16x3"])
+        assert np.array_equal(job.energy("fp64", per_triple=True)[2], ref["fp64"])
