@@ -29,13 +29,15 @@ extern "C" {
 
 typedef enum te_status {
   TE_OK = 0,
-  TE_PENDING = 1,     /* te_poll only: the job has not finished            */
+  TE_PENDING = 1,     /* te_poll: the job has not finished;
+                         te_energy_checkpointed: triples remain           */
   TE_EINVAL = -1,     /* bad argument (sizes, NULL pointers, bad values)   */
   TE_ENOMEM = -2,     /* the job cannot fit in the HBM budget              */
   TE_EDEVICE = -3,    /* a HIP runtime call failed                         */
   TE_EBUSY = -4,      /* the server is shutting down / queue full          */
   TE_ENOTFOUND = -5,  /* unknown or already-collected ticket               */
-  TE_ECANCELED = -6   /* the server was destroyed before the job ran       */
+  TE_ECANCELED = -6,  /* the server was destroyed before the job ran       */
+  TE_EIO = -7         /* reading or writing a checkpoint file failed       */
 } te_status;
 
 /* Arithmetic of the W contractions (Eqs. 2 and 5). In every mode the
@@ -144,6 +146,47 @@ te_status te_energy(te_job job, te_precision prec, double *e_t, double *per_trip
  * sum, per_triple (optional, host [n]) each weighted partial. */
 te_status te_energy_triples(te_job job, te_precision prec, const int32_t *ijk, int64_t n,
                             double *e_sum, double *per_triple, te_stats *st);
+
+/* E(T) split by perturbation order into the two parts that make up the (T)
+ * correction (its fourth- and fifth-order connected-triples terms, as the
+ * introduction of the paper describes them): E[4] collects the W Z / D
+ * terms of Eq. 1, which do not involve the singles, and E[5] the V Z / D
+ * terms, V from Eq. 3 (linear in t1); E(T) = E[4] + E[5]. ijk / n as for
+ * te_energy_triples; ijk == NULL takes every triple in te_triple_list order
+ * (n is then ignored). e4_sum / e5_sum (optional) receive the two sums over
+ * the triples, e4 / e5 (optional, host arrays of the triple count) each
+ * triple's weighted parts. Errors as te_energy_triples. */
+te_status te_energy_terms(te_job job, te_precision prec, const int32_t *ijk, int64_t n,
+                          double *e4_sum, double *e5_sum, double *e4, double *e5,
+                          te_stats *st);
+
+/* Whole-job evaluation that survives interruption. The triples, in
+ * te_triple_list order, are cut into chunks of `chunk` consecutive triples;
+ * each finished chunk's per-triple E[4] and E[5] parts (te_energy_terms) are
+ * appended to the checkpoint file at `path` as one checksummed record, and
+ * the file is flushed to disk before the next chunk starts. A file left by
+ * an earlier call with the same o, v, naux, precision, chunk and `tag` is
+ * resumed: intact records are kept, a torn last record is dropped, and only
+ * the missing chunks are evaluated. `tag` is any 64-bit value the caller
+ * uses to name the inputs (a hash of them, say); a file whose header does
+ * not match is rejected with TE_EINVAL and left as it is. max_chunks > 0
+ * stops after that many newly evaluated chunks (runs under a wall-time
+ * limit); 0 runs to the end. Returns TE_OK when every chunk is recorded,
+ * with e_t / e4_sum / e5_sum (optional) set to the sums over all triples,
+ * taken in triple order with compensation on the host: an interrupted and
+ * resumed run gives the same bits as one that ran through. Returns
+ * TE_PENDING while chunks remain (outputs untouched). st (optional)
+ * describes the work of this call only. File errors: TE_EIO. */
+te_status te_energy_checkpointed(te_job job, te_precision prec, const char *path, uint64_t tag,
+                                 int64_t chunk, int64_t max_chunks, double *e_t,
+                                 double *e4_sum, double *e5_sum, te_stats *st);
+
+/* Progress of a checkpoint file without a device or a job: checks its header
+ * against the given problem (TE_EINVAL on a mismatch, TE_ENOTFOUND when the
+ * file does not exist) and counts its intact chunk records. Reads only. */
+te_status te_checkpoint_scan(const char *path, int32_t o, int32_t v, int32_t naux,
+                             te_precision prec, uint64_t tag, int64_t chunk,
+                             int64_t *chunks_done, int64_t *chunks_total);
 
 te_status te_free(te_job job);
 

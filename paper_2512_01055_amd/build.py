@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libte.so")
-SOURCES = ["te_wbuild.hip", "te_kernels.hip", "te_api.cpp", "te_server.cpp"]
+SOURCES = ["te_wbuild.hip", "te_kernels.hip", "te_api.cpp", "te_server.cpp", "te_checkpoint.cpp"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -503,6 +503,16 @@ static void assemble_slice(Job &J, Prec p, int occ, void *slot, double *tmp64, h
     HIPCHK(launch_to_bf16_parts(tmp64, (uint16_t *)slot, n, 3, s));
 }
 
+std::vector<int> checked_triples(const Job &J, const int32_t *ijk, int64_t n) {
+  if (n < 0 || (n > 0 && !ijk)) throw Fail(TE_EINVAL, "bad triple list");
+  for (int64_t t = 0; t < n; ++t) {
+    int i = ijk[3 * t], j = ijk[3 * t + 1], k = ijk[3 * t + 2];
+    if (i < 0 || i > j || j > k || k >= J.o || (i == j && j == k))
+      throw Fail(TE_EINVAL, "triple " + std::to_string(t) + " is not 0<=i<=j<=k<o, not all equal");
+  }
+  return std::vector<int>(ijk, ijk + 3 * n);
+}
+
 void resident_k_views(const Job &J, int i, int j, int k, EItem &e) {
   const long o = J.o, vp = J.vp;
   const double *K = J.K.as<double>();
@@ -522,7 +532,7 @@ static void assemble_k_block(Job &J, int p, int q, double *dst, hipStream_t s) {
 }
 
 void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double *per_triple,
-                 te_stats *st) {
+                 te_stats *st, const SplitOut *split) {
   auto t0 = std::chrono::steady_clock::now();
   const int pslot = (p == Prec::BF16X2) ? (int)Prec::BF16X3 : (int)p;
   if (J.xc.pslot >= 0 && J.xc.pslot != pslot) {   // slices of another precision
@@ -547,20 +557,27 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
 
   // scratch: W for two batches, partials for two batches, per-triple results,
   // and (on the fly) three (ov|ov) blocks per triple of the two batches
-  DBuf wbuf, part, eout, esum, witems, eitems, ritems, kbuf;
+  // (E[4] and E[5] partials per sextet; the two parts per triple when split
+  // output is asked for)
+  DBuf wbuf, part, eout, e4out, e5out, esum, witems, eitems, ritems, kbuf;
   const size_t kblk = (size_t)vp * vp;
   auto scratch = [&] {
     wbuf.alloc(2 * (size_t)B * 3 * vp3 * osz, &J.used, J.budget);
-    part.alloc(2 * (size_t)B * J.nsext * 8, &J.used, J.budget);
+    part.alloc(2 * (size_t)B * 2 * J.nsext * 8, &J.used, J.budget);
     eout.alloc((size_t)ntr * 8, &J.used, J.budget);
-    esum.alloc(8, &J.used, J.budget);
+    if (split) {
+      e4out.alloc((size_t)ntr * 8, &J.used, J.budget);
+      e5out.alloc((size_t)ntr * 8, &J.used, J.budget);
+    }
+    esum.alloc(3 * 8, &J.used, J.budget);
     if (fly) kbuf.alloc(2 * (size_t)B * 3 * kblk * 8, &J.used, J.budget);
   };
   try {
     scratch();
   } catch (const Fail &f) {
     if (f.s != TE_ENOMEM || !J.xc.mem.p) throw;
-    wbuf.release(); part.release(); eout.release(); esum.release(); kbuf.release();
+    wbuf.release(); part.release(); eout.release(); e4out.release(); e5out.release();
+    esum.release(); kbuf.release();
     J.xc.release();                  // a kept cache gives way to this call's scratch
     scratch();
   }
@@ -626,11 +643,14 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
       }
       e.W = W; e.t1 = J.t1.as<double>();
       e.eo = J.eo.as<double>(); e.ev = J.ev.as<double>(); e.sext = J.sext.as<int>();
-      e.part = part.as<double>() + ((size_t)sl * B + q) * J.nsext;
+      e.part = part.as<double>() + ((size_t)sl * B + q) * 2 * J.nsext;
+      e.part5 = e.part + J.nsext;
       e.o = o; e.v = J.v; e.vp = vp; e.nT = vp / BOX; e.i = i; e.j = j; e.k = k;
       e.nsext = J.nsext;
       RItem &r = ri[pos];
-      r.part = e.part; r.out = eout.as<double>() + t; r.n = J.nsext;
+      r.part = e.part; r.part5 = e.part5; r.out = eout.as<double>() + t; r.n = J.nsext;
+      r.out4 = split ? e4out.as<double>() + t : nullptr;
+      r.out5 = split ? e5out.as<double>() + t : nullptr;
       r.w = 2.0 - (i == j) - (j == k);
     }
   }
@@ -685,14 +705,25 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
     HIPCHK(hipEventRecord(J.ev_e[slot], J.s_main));
   }
   HIPCHK(launch_sum(eout.as<double>(), ntr, esum.as<double>(), J.s_main));
-  double E = 0.0;
-  HIPCHK(hipMemcpyAsync(&E, esum.p, 8, hipMemcpyDeviceToHost, J.s_main));
+  if (split) {
+    HIPCHK(launch_sum(e4out.as<double>(), ntr, esum.as<double>() + 1, J.s_main));
+    HIPCHK(launch_sum(e5out.as<double>(), ntr, esum.as<double>() + 2, J.s_main));
+  }
+  double Es[3] = {0.0, 0.0, 0.0};
+  HIPCHK(hipMemcpyAsync(Es, esum.p, 3 * 8, hipMemcpyDeviceToHost, J.s_main));
   if (per_triple)
     HIPCHK(hipMemcpyAsync(per_triple, eout.p, ntr * 8, hipMemcpyDeviceToHost, J.s_main));
+  if (split && split->pt4)
+    HIPCHK(hipMemcpyAsync(split->pt4, e4out.p, ntr * 8, hipMemcpyDeviceToHost, J.s_main));
+  if (split && split->pt5)
+    HIPCHK(hipMemcpyAsync(split->pt5, e5out.p, ntr * 8, hipMemcpyDeviceToHost, J.s_main));
   HIPCHK(hipStreamSynchronize(J.s_main));
   if (fly) J.xc.held = after;
   auto t2 = std::chrono::steady_clock::now();
+  const double E = Es[0];
   if (e_sum) *e_sum = E;
+  if (split && split->e4_sum) *split->e4_sum = Es[1];
+  if (split && split->e5_sum) *split->e5_sum = Es[2];
   if (st) {
     st->seconds = std::chrono::duration<double>(t2 - t0).count();
     st->stage_seconds = std::chrono::duration<double>(t1 - t0).count();
@@ -865,13 +896,6 @@ Job *make_job(const te_problem *P, const te_config *cfg_in, const JobOpts *opts)
 using namespace te;
 
 // ------------------------------------------------------------ C ABI
-#define TE_GUARD_BEGIN try {
-#define TE_GUARD_END                                                  \
-  }                                                                   \
-  catch (const Fail &f) { return set_error(f.s, f.msg); }             \
-  catch (const std::bad_alloc &) { return set_error(TE_ENOMEM, "host allocation failed"); } \
-  catch (...) { return set_error(TE_EDEVICE, "unexpected exception"); }
-
 extern "C" {
 
 te_status te_init(const te_problem *prob, const te_config *cfg, te_job *out) {
@@ -881,11 +905,6 @@ te_status te_init(const te_problem *prob, const te_config *cfg, te_job *out) {
   *out = reinterpret_cast<te_job>(J);
   return TE_OK;
   TE_GUARD_END
-}
-
-static Prec to_prec(te_precision p) {
-  if (p < TE_FP64 || p > TE_BF16X2) throw Fail(TE_EINVAL, "bad precision");
-  return static_cast<Prec>(p);
 }
 
 te_status te_energy(te_job job, te_precision prec, double *e_t, double *per_triple,
@@ -912,22 +931,36 @@ te_status te_energy_triples(te_job job, te_precision prec, const int32_t *ijk, i
                             double *e_sum, double *per_triple, te_stats *st) {
   TE_GUARD_BEGIN
   if (!job) return set_error(TE_EINVAL, "job is NULL");
-  if (n < 0 || (n > 0 && !ijk)) return set_error(TE_EINVAL, "bad triple list");
   Job &J = *reinterpret_cast<Job *>(job);
   Prec p = to_prec(prec);
-  for (int64_t t = 0; t < n; ++t) {
-    int i = ijk[3 * t], j = ijk[3 * t + 1], k = ijk[3 * t + 2];
-    if (i < 0 || i > j || j > k || k >= J.o || (i == j && j == k))
-      return set_error(TE_EINVAL, "triple " + std::to_string(t) + " is not 0<=i<=j<=k<o, not all equal");
-  }
+  std::vector<int> t = checked_triples(J, ijk, n);
   HIPCHK(hipSetDevice(J.device));
   double E = 0.0;
   te_stats s{};
-  if (n > 0) {
-    std::vector<int> t(ijk, ijk + 3 * n);
-    run_triples(J, p, t.data(), (long)n, &E, per_triple, &s);
-  }
+  if (n > 0) run_triples(J, p, t.data(), (long)n, &E, per_triple, &s);
   if (e_sum) *e_sum = E;
+  if (st) *st = s;
+  return TE_OK;
+  TE_GUARD_END
+}
+
+te_status te_energy_terms(te_job job, te_precision prec, const int32_t *ijk, int64_t n,
+                          double *e4_sum, double *e5_sum, double *e4, double *e5,
+                          te_stats *st) {
+  TE_GUARD_BEGIN
+  if (!job) return set_error(TE_EINVAL, "job is NULL");
+  Job &J = *reinterpret_cast<Job *>(job);
+  Prec p = to_prec(prec);
+  std::vector<int> t = ijk ? checked_triples(J, ijk, n) : triple_list_host(J.o);
+  const long nt = (long)t.size() / 3;
+  HIPCHK(hipSetDevice(J.device));
+  SplitOut so;
+  double E4 = 0.0, E5 = 0.0;
+  so.e4_sum = &E4; so.e5_sum = &E5; so.pt4 = e4; so.pt5 = e5;
+  te_stats s{};
+  if (nt > 0) run_triples(J, p, t.data(), nt, nullptr, nullptr, &s, &so);
+  if (e4_sum) *e4_sum = E4;
+  if (e5_sum) *e5_sum = E5;
   if (st) *st = s;
   return TE_OK;
   TE_GUARD_END
@@ -1014,6 +1047,7 @@ const char *te_strerror(te_status s) {
     case TE_EBUSY: return "busy";
     case TE_ENOTFOUND: return "unknown ticket";
     case TE_ECANCELED: return "canceled";
+    case TE_EIO: return "checkpoint file I/O failed";
   }
   return "unknown status";
 }

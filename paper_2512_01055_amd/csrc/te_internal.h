@@ -47,14 +47,17 @@ struct EItem {
   const double *eo;    // [o]
   const double *ev;    // [vp]
   const int *sext;     // packed box triples A>=B>=C: A | B<<10 | C<<20
-  double *part;        // [nsext] partial sums
+  double *part;        // [nsext] partial sums of the W Z / D terms (E[4])
+  double *part5;       // [nsext] partial sums of the V Z / D terms (E[5])
   int o, v, vp, nT, i, j, k, nsext;
 };
 
-// Per-triple reduction: e = w * sum(part[0..n)).
+// Per-triple reduction: S4 = sum(part[0..n)), S5 = sum(part5[0..n)), both in a
+// fixed order; e = w (S4 + S5).
 struct RItem {
-  const double *part;
-  double *out;
+  const double *part, *part5;
+  double *out;          // w (S4 + S5)
+  double *out4, *out5;  // w S4, w S5 (optional)
   int n;
   double w;
 };

@@ -24,6 +24,19 @@ void hip_check(hipError_t e, const char *what, int line);
 
 te_status set_error(te_status s, const std::string &m);
 
+// Body of every C-ABI entry point: exceptions become status codes.
+#define TE_GUARD_BEGIN try {
+#define TE_GUARD_END                                                                        \
+  }                                                                                         \
+  catch (const ::te::Fail &f) { return ::te::set_error(f.s, f.msg); }                       \
+  catch (const std::bad_alloc &) { return ::te::set_error(TE_ENOMEM, "host allocation failed"); } \
+  catch (...) { return ::te::set_error(TE_EDEVICE, "unexpected exception"); }
+
+inline Prec to_prec(te_precision p) {
+  if (p < TE_FP64 || p > TE_BF16X2) throw Fail(TE_EINVAL, "bad precision");
+  return static_cast<Prec>(p);
+}
+
 // One device allocation carved up on the host: first fit over a free list,
 // 256-byte granules. Freeing never touches the device, so a server can
 // recycle memory of finished jobs while other work is in flight (it frees a
@@ -113,9 +126,17 @@ size_t job_footprint(int o, int v, int naux, Prec p);
 int out_bytes(Prec p);
 const Operands &ensure_prec(Job &J, Prec p);
 void resident_k_views(const Job &J, int i, int j, int k, EItem &e);
+// Optional E[4] / E[5] outputs of run_triples (any pointer may be null).
+struct SplitOut {
+  double *e4_sum = nullptr, *e5_sum = nullptr;   // sums over the listed triples
+  double *pt4 = nullptr, *pt5 = nullptr;         // host [ntr] per-triple parts
+};
 void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double *per_triple,
-                 te_stats *st);
+                 te_stats *st, const SplitOut *split = nullptr);
 std::vector<int> triple_list_host(int o);
+// Copy of a caller's [n][3] triple list after checking 0 <= i <= j <= k < o,
+// not all equal (TE_EINVAL otherwise).
+std::vector<int> checked_triples(const Job &J, const int32_t *ijk, int64_t n);
 std::vector<int> sextet_list(int nT);
 double flops_per_triple(int o, int v);
 int64_t plan_slice_loads(int o, int S, int B);

@@ -34,7 +34,7 @@ __global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ it
                                                     const int *__restrict__ blk_item,
                                                     int blks_per_item, long total) {
   __shared__ double box[6 * BX_S];
-  __shared__ double red[WG / 64];
+  __shared__ double red[2 * (WG / 64)];
   const int tid = threadIdx.x;
   const long bid = blockIdx.x;
   int it;
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ it
 
   const double eijk = (e.eo[i] + e.eo[j]) + e.eo[k];
   const double *t1i = e.t1 + (long)i * vp, *t1j = e.t1 + (long)j * vp, *t1k = e.t1 + (long)k * vp;
-  double acc = 0.0;
+  double acc4 = 0.0, acc5 = 0.0;   // W Z / D and V Z / D (E[4] and E[5] parts)
 #pragma unroll 1
   for (int s = 0; s < 6; ++s) {
     if (canon[s] != s) continue;
@@ -101,20 +101,32 @@ __global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ it
                         + gld(t1j + b) * gld(e.Kik + a * e.kld + c)
                         + gld(t1k + c) * gld(e.Kij + a * e.kld + b);
         const double d = ((eijk - gld(e.ev + a)) - gld(e.ev + b)) - gld(e.ev + c);
-        acc += (w0 + vt) * z / d;
+        const double q = z / d;
+        acc4 += w0 * q;
+        acc5 += vt * q;
       }
     }
   }
   // fixed-order reduction: butterfly within the wave, then waves in order
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  for (int off = 32; off > 0; off >>= 1) {
+    acc4 += __shfl_xor(acc4, off, 64);
+    acc5 += __shfl_xor(acc5, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = acc4;
+    red[WG / 64 + (tid >> 6)] = acc5;
+  }
   __syncthreads();
   if (tid == 0) {
-    double sum = red[0];
+    double s4 = red[0], s5 = red[WG / 64];
 #pragma unroll
-    for (int q = 1; q < WG / 64; ++q) sum += red[q];
-    e.part[local] = sum;
+    for (int q = 1; q < WG / 64; ++q) {
+      s4 += red[q];
+      s5 += red[WG / 64 + q];
+    }
+    gst(e.part + local, s4);
+    gst(e.part5 + local, s5);
   }
 }
 
@@ -136,10 +148,19 @@ __device__ inline double block_sum(double x, double *red) {
 __global__ __launch_bounds__(WG) void reduce_kernel(const RItem *__restrict__ items) {
   __shared__ double red[WG / 64];
   const RItem r = items[blockIdx.x];
-  double x = 0.0;
-  for (int q = threadIdx.x; q < r.n; q += WG) x += r.part[q];
-  double s = block_sum(x, red);
-  if (threadIdx.x == 0) *r.out = r.w * s;
+  double x4 = 0.0, x5 = 0.0;
+  for (int q = threadIdx.x; q < r.n; q += WG) {
+    x4 += r.part[q];
+    x5 += r.part5[q];
+  }
+  const double s4 = block_sum(x4, red);
+  __syncthreads();                       // thread 0 has read red
+  const double s5 = block_sum(x5, red);
+  if (threadIdx.x == 0) {
+    *r.out = r.w * (s4 + s5);
+    if (r.out4) *r.out4 = r.w * s4;
+    if (r.out5) *r.out5 = r.w * s5;
+  }
 }
 
 __global__ __launch_bounds__(1024) void sum_kernel(const double *__restrict__ x, long n,

@@ -96,7 +96,7 @@ struct SJob {
 constexpr int MAX_ITEMS = 4096;
 constexpr int NSLOT = 3;   // rounds in flight
 constexpr long MAX_TILES = 262144;
-constexpr long MAX_BLKS = 4L << 20;
+constexpr long MAX_BLKS = 2L << 20;
 
 struct Slot {
   DBuf W, part, witems, eitems, ritems, tmap, bmap;
@@ -329,11 +329,13 @@ ServerImpl::Launch ServerImpl::launch_round() {
     e.W = W; resident_k_views(J, i, jj, k, e); e.t1 = J.t1.as<double>();
     e.eo = J.eo.as<double>(); e.ev = J.ev.as<double>(); e.sext = J.sext.as<int>();
     e.part = S.part.as<double>() + b0;
+    e.part5 = S.part.as<double>() + MAX_BLKS + b0;
     e.o = J.o; e.v = J.v; e.vp = (int)vp; e.nT = (int)(vp / BOX);
     e.i = i; e.j = jj; e.k = k; e.nsext = J.nsext;
     for (long x = 0; x < J.nsext; ++x) S.h_bmap[b0 + x] = q;
     RItem &r = S.h_ri[q];
-    r.part = e.part; r.out = j->eout.as<double>() + t; r.n = J.nsext;
+    r.part = e.part; r.part5 = e.part5; r.out = j->eout.as<double>() + t; r.n = J.nsext;
+    r.out4 = r.out5 = nullptr;
     r.w = 2.0 - (i == jj) - (jj == k);
     t0 += nt_;
     b0 += J.nsext;
@@ -439,7 +441,7 @@ void ServerImpl::start() {
   wcap = std::min<size_t>((size_t)3 << 30, budget / 8);
   for (Slot &S : slot) {
     S.W.alloc(wcap, nullptr, 0);
-    S.part.alloc(MAX_BLKS * 8, nullptr, 0);
+    S.part.alloc(2 * (size_t)MAX_BLKS * 8, nullptr, 0);
     S.witems.alloc(MAX_ITEMS * sizeof(WItem), nullptr, 0);
     S.eitems.alloc(MAX_ITEMS * sizeof(EItem), nullptr, 0);
     S.ritems.alloc(MAX_ITEMS * sizeof(RItem), nullptr, 0);
@@ -453,7 +455,7 @@ void ServerImpl::start() {
     HIPCHK(hipEventCreateWithFlags(&S.ev_w, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&S.ev_e, hipEventDisableTiming));
   }
-  const size_t scratch = NSLOT * (wcap + MAX_BLKS * 8 + (MAX_BLKS + MAX_ITEMS) * 4);
+  const size_t scratch = NSLOT * (wcap + 2 * MAX_BLKS * 8 + (MAX_BLKS + MAX_ITEMS) * 4);
   if (budget <= scratch + ((size_t)1 << 28))
     throw Fail(TE_ENOMEM, "HBM budget too small for the server's round scratch");
   arena.init(budget - scratch);
@@ -511,13 +513,6 @@ void ServerImpl::shutdown() {
 }  // namespace te
 
 using namespace te;
-
-#define TE_GUARD_BEGIN try {
-#define TE_GUARD_END                                                                        \
-  }                                                                                         \
-  catch (const Fail &f) { return set_error(f.s, f.msg); }                                   \
-  catch (const std::bad_alloc &) { return set_error(TE_ENOMEM, "host allocation failed"); } \
-  catch (...) { return set_error(TE_EDEVICE, "unexpected exception"); }
 
 extern "C" {
 

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libte.so")
 
-OK, PENDING, EINVAL, ENOMEM, EDEVICE, EBUSY, ENOTFOUND, ECANCELED = 0, 1, -1, -2, -3, -4, -5, -6
+OK, PENDING, EINVAL, ENOMEM, EDEVICE, EBUSY, ENOTFOUND, ECANCELED, EIO = 0, 1, -1, -2, -3, -4, -5, -6, -7
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3}
 X_MODES = {"auto": 0, "resident": 1, "on_the_fly": 2}
 
@@ -60,7 +60,8 @@ class ServerConfig(C.Structure):
 
 _lib: Optional[C.CDLL] = None
 
-EXPORTS = ["te_init", "te_energy", "te_energy_triples", "te_free", "te_num_triples",
+EXPORTS = ["te_init", "te_energy", "te_energy_triples", "te_energy_terms",
+           "te_energy_checkpointed", "te_checkpoint_scan", "te_free", "te_num_triples",
            "te_triple_list", "te_flops_per_triple", "te_plan_slice_loads", "te_server_create", "te_submit",
            "te_poll", "te_wait", "te_server_destroy", "te_strerror", "te_last_error"]
 
@@ -86,6 +87,14 @@ def lib() -> C.CDLL:
     L.te_energy.argtypes = [P, S, C.POINTER(C.c_double), C.c_void_p, C.POINTER(Stats)]
     L.te_energy_triples.argtypes = [P, S, C.c_void_p, C.c_int64, C.POINTER(C.c_double),
                                     C.c_void_p, C.POINTER(Stats)]
+    D = C.POINTER(C.c_double)
+    L.te_energy_terms.argtypes = [P, S, C.c_void_p, C.c_int64, D, D, C.c_void_p, C.c_void_p,
+                                  C.POINTER(Stats)]
+    L.te_energy_checkpointed.argtypes = [P, S, C.c_char_p, C.c_uint64, C.c_int64, C.c_int64,
+                                         D, D, D, C.POINTER(Stats)]
+    L.te_checkpoint_scan.argtypes = [C.c_char_p, C.c_int32, C.c_int32, C.c_int32, S,
+                                     C.c_uint64, C.c_int64, C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64)]
     L.te_free.argtypes = [P]
     L.te_num_triples.argtypes = [C.c_int32]
     L.te_num_triples.restype = C.c_int64
@@ -104,7 +113,8 @@ def lib() -> C.CDLL:
     L.te_strerror.argtypes = [S]
     L.te_strerror.restype = C.c_char_p
     L.te_last_error.restype = C.c_char_p
-    for f in ("te_init", "te_energy", "te_energy_triples", "te_free", "te_triple_list",
+    for f in ("te_init", "te_energy", "te_energy_triples", "te_energy_terms",
+              "te_energy_checkpointed", "te_checkpoint_scan", "te_free", "te_triple_list",
               "te_server_create", "te_submit", "te_poll", "te_wait", "te_server_destroy"):
         getattr(L, f).restype = S
     _lib = L
@@ -217,6 +227,39 @@ class Job:
                                    C.byref(e), pt.ctypes.data, C.byref(st)))
         return e.value, pt, st.as_dict()
 
+    def energy_terms(self, precision: str = "fp64", triples: Optional[Sequence] = None):
+        """E(T) split as (E4, E5, e4, e5, stats): the W Z / D and V Z / D parts,
+        summed and per triple (all triples in triple_list order when triples
+        is None)."""
+        L = lib()
+        if triples is None:
+            t, n = None, int(L.te_num_triples(self.o))
+        else:
+            t = np.ascontiguousarray(np.asarray(triples, dtype=np.int32).reshape(-1, 3))
+            n = len(t)
+        e4, e5 = np.zeros(n), np.zeros(n)
+        E4, E5 = C.c_double(), C.c_double()
+        st = Stats()
+        _check(L.te_energy_terms(self._h, PRECISIONS[precision],
+                                 None if t is None else t.ctypes.data, n, C.byref(E4),
+                                 C.byref(E5), e4.ctypes.data, e5.ctypes.data, C.byref(st)))
+        return E4.value, E5.value, e4, e5, st.as_dict()
+
+    def energy_checkpointed(self, precision: str, path: str, chunk: int, tag: int = 0,
+                            max_chunks: int = 0):
+        """Whole-job evaluation recorded chunk by chunk in `path` (resumed
+        when the file exists). Returns (done, E, E4, E5, stats); done is False
+        while chunks remain (max_chunks reached), with the energies None."""
+        L = lib()
+        E, E4, E5 = C.c_double(), C.c_double(), C.c_double()
+        st = Stats()
+        s = _check(L.te_energy_checkpointed(self._h, PRECISIONS[precision],
+                                            os.fsencode(path), tag, chunk, max_chunks,
+                                            C.byref(E), C.byref(E4), C.byref(E5), C.byref(st)))
+        if s == PENDING:
+            return False, None, None, None, st.as_dict()
+        return True, E.value, E4.value, E5.value, st.as_dict()
+
     def free(self) -> None:
         if getattr(self, "_h", None):
             _check(lib().te_free(self._h))
@@ -315,3 +358,13 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def checkpoint_scan(path: str, o: int, v: int, naux: int, precision: str, chunk: int,
+                    tag: int = 0):
+    """(chunks recorded intact, chunks in the job) of a checkpoint file; no
+    device needed."""
+    done, total = C.c_int64(), C.c_int64()
+    _check(lib().te_checkpoint_scan(os.fsencode(path), o, v, naux, PRECISIONS[precision], tag,
+                                    chunk, C.byref(done), C.byref(total)))
+    return done.value, total.value

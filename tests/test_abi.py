@@ -100,3 +100,66 @@ def test_slice_plan_counts():
     assert lib.te_plan_slice_loads(100, 45, 1) < 2000
     assert lib.te_plan_slice_loads(0, 10, 1) == -1
     assert lib.te_plan_slice_loads(10, 2, 1) == -1
+
+
+# checkpoint files written from Python in the layout te.h documents
+def _fnv(b: bytes, h: int = 1469598103934665603) -> int:
+    for c in b:
+        h = ((h ^ c) * 1099511628211) & (2 ** 64 - 1)
+    return h
+
+
+def _ckpt_header(o, v, naux, prec, tag, chunk):
+    import struct
+    n = o * (o + 1) * (o + 2) // 6 - o
+    body = b"TECKPT01" + struct.pack("<iiiiQqq", o, v, naux, prec, tag, n, chunk)
+    return body + struct.pack("<Q", _fnv(body)), n
+
+
+def _ckpt_record(first, vals4, vals5):
+    import struct
+    body = struct.pack("<qq", first, len(vals4)) + struct.pack(f"<{len(vals4)}d", *vals4) \
+        + struct.pack(f"<{len(vals5)}d", *vals5)
+    return body + struct.pack("<Q", _fnv(body))
+
+
+def test_checkpoint_scan_counts_intact_records(tmp_path):
+    o, v, naux, chunk, tag = 4, 10, 7, 5, 99
+    head, n = _ckpt_header(o, v, naux, 0, tag, chunk)
+    assert n == 16                                   # 4 chunks: 5, 5, 5, 1
+    recs = [_ckpt_record(f, [0.1 * f + q for q in range(min(chunk, n - f))],
+                         [-q for q in range(min(chunk, n - f))]) for f in (0, 5, 10)]
+    p = tmp_path / "run.ckpt"
+    assert te.lib().te_checkpoint_scan(str(p).encode(), o, v, naux, 0, tag, chunk, None,
+                                       None) == te.ENOTFOUND
+    p.write_bytes(head + b"".join(recs))
+    assert te.checkpoint_scan(str(p), o, v, naux, "fp64", chunk, tag) == (3, 4)
+    # a torn last record does not count; the scan leaves the file as it is
+    p.write_bytes(head + b"".join(recs)[:-3])
+    assert te.checkpoint_scan(str(p), o, v, naux, "fp64", chunk, tag) == (2, 4)
+    assert p.stat().st_size == len(head) + sum(map(len, recs)) - 3
+    # a flipped byte ends the intact part at the record before it
+    bad = bytearray(head + b"".join(recs))
+    bad[len(head) + len(recs[0]) + 20] ^= 1
+    p.write_bytes(bytes(bad))
+    assert te.checkpoint_scan(str(p), o, v, naux, "fp64", chunk, tag) == (1, 4)
+    # the last, shorter chunk and a duplicate record
+    p.write_bytes(head + b"".join(recs) + _ckpt_record(15, [1.0], [2.0]) + recs[0])
+    assert te.checkpoint_scan(str(p), o, v, naux, "fp64", chunk, tag) == (4, 4)
+
+
+def test_checkpoint_scan_rejects_other_problems(tmp_path):
+    o, v, naux, chunk = 4, 10, 7, 5
+    head, _ = _ckpt_header(o, v, naux, 2, 5, chunk)
+    p = tmp_path / "run.ckpt"
+    p.write_bytes(head)
+    assert te.checkpoint_scan(str(p), o, v, naux, "bf16x3", chunk, 5) == (0, 4)
+    for args in ((o, v, naux, "fp64", chunk, 5), (o, v, naux, "bf16x3", chunk, 6),
+                 (o, v + 1, naux, "bf16x3", chunk, 5), (o, v, naux, "bf16x3", chunk + 1, 5)):
+        with pytest.raises(te.TeError) as ei:
+            te.checkpoint_scan(str(p), *args)
+        assert ei.value.status == te.EINVAL
+    p.write_bytes(b"not a checkpoint at all" * 4)
+    with pytest.raises(te.TeError) as ei:
+        te.checkpoint_scan(str(p), o, v, naux, "bf16x3", chunk, 5)
+    assert ei.value.status == te.EINVAL

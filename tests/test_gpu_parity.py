@@ -302,3 +302,65 @@ def test_slice_cache_kept_across_calls():
         assert np.array_equal(np.concatenate(pieces), ref["fp64"])
         assert np.array_equal(job.energy("bf16x3", per_triple=True)[2], ref["bf16x3"])
         assert np.array_equal(job.energy("fp64", per_triple=True)[2], ref["fp64"])
+
+
+def test_energy_terms_match_oracle():
+    """E[4] (W Z / D) and E[5] (V Z / D) per triple against the oracle's
+    split, in every precision; the parts add up to the per-triple total."""
+    P = make_problem(6, 30, 90, 1)
+    ints = oracle.DFIntegrals(P.B_oo, P.B_ov, P.B_vv, max_cached=P.o)
+    (E4r, E5r), parts = oracle.energy(P.eps_occ, P.eps_vir, P.t1, P.t2, ints, split=True)
+    e4r = np.array([p[3] for p in parts])
+    e5r = np.array([p[4] for p in parts])
+    assert abs(E5r) > 1e-4 * abs(E4r)               # the singles part is exercised
+    te = _te()
+    sub = sample_triples(P.o, 10, 7)
+    allt = te.triple_list(P.o)
+    idx = [int(np.nonzero((allt == s).all(1))[0][0]) for s in sub]
+    with te.Job(P, device=0) as job:
+        for prec in PRECS:
+            E4, E5, e4, e5, st = job.energy_terms(prec)
+            _, _, pt = job.energy(prec, per_triple=True)
+            tol = 1e-11 if prec == "fp64" else TOL[prec]
+            scale = np.maximum(np.abs(e4r), 1.0 if prec != "fp64" else 0.0)
+            print(f"\n[{prec}] E4 {E4:.12e} ({E4r:.12e})  E5 {E5:.12e} ({E5r:.12e})", flush=True)
+            assert np.all(np.abs(e4 - e4r) <= tol * scale)
+            assert np.all(np.abs(e5 - e5r) <= tol * scale)
+            assert abs(E4 - E4r) <= tol * max(abs(E4r), 1.0)
+            assert abs(E5 - E5r) <= tol * max(abs(E4r), 1.0)
+            assert np.all(np.abs(e4 + e5 - pt) <= 1e-14 * np.abs(pt))
+            s4, s5, p4, p5, _ = job.energy_terms(prec, triples=sub)
+            assert np.array_equal(p4, e4[idx]) and np.array_equal(p5, e5[idx])
+
+
+def test_checkpointed_run_resumes_to_the_same_bits(tmp_path):
+    te = _te()
+    P = make_problem(7, 40, 30, 41)
+    n = int(te.lib().te_num_triples(P.o))          # 77 triples, chunks of 9
+    with te.Job(P, device=0) as job:
+        E4r, E5r, _, _, _ = job.energy_terms("fp64")
+        a = str(tmp_path / "a.ckpt")
+        done, E, E4, E5, st = job.energy_checkpointed("fp64", a, chunk=9, tag=7)
+        assert done and st["n_triples"] == n
+        assert abs(E4 - E4r) <= 1e-14 * abs(E4r) and abs(E5 - E5r) <= 1e-13 * abs(E4r)
+        assert E == E4 + E5
+        # stopped after three chunks, then the file torn in its last record
+        b = str(tmp_path / "b.ckpt")
+        done, *_, st = job.energy_checkpointed("fp64", b, chunk=9, tag=7, max_chunks=3)
+        assert not done and st["n_triples"] == 27
+        assert te.checkpoint_scan(b, P.o, P.v, P.naux, "fp64", 9, 7) == (3, 9)
+        size = os.path.getsize(b)
+        with open(b, "r+b") as f:
+            f.truncate(size - 5)
+        assert te.checkpoint_scan(b, P.o, P.v, P.naux, "fp64", 9, 7) == (2, 9)
+        done, E_b, E4_b, E5_b, st = job.energy_checkpointed("fp64", b, chunk=9, tag=7)
+        assert done and st["n_triples"] == n - 18
+        assert (E_b, E4_b, E5_b) == (E, E4, E5)
+        # complete file: nothing left to evaluate
+        done, E_c, _, _, st = job.energy_checkpointed("fp64", b, chunk=9, tag=7)
+        assert done and st["n_triples"] == 0 and E_c == E
+        # another tag (other inputs) is refused and the file kept
+        size = os.path.getsize(b)
+        with pytest.raises(te.TeError) as ei:
+            job.energy_checkpointed("fp64", b, chunk=9, tag=8)
+        assert ei.value.status == te.EINVAL and os.path.getsize(b) == size

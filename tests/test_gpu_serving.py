@@ -61,7 +61,7 @@ def test_admission_one_resident_job_at_a_time():
     assert got == alone
 
 
-# 1 GiB: three round-scratch slots take ~530 MiB, the arena keeps ~490 MiB,
+# 1 GiB: three round-scratch slots take ~500 MiB, the arena keeps ~520 MiB,
 # room for one o=14 v=128 job (~350 MiB) at a time
 TIGHT = 1 << 30
 
