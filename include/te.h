@@ -94,6 +94,13 @@ typedef struct te_config {
   int validate;         /* 1: reject non-finite inputs and t2 asymmetry > 1e-12   */
   te_xmode x_mode;
   int x_cache_slices;   /* on-the-fly mode: slices kept resident; 0: automatic    */
+  /* 1: t2 stays in host memory (for t2 larger than HBM). For each occupied
+   * index a cache slot takes, its t2 panels (the column panel t2[:, p] and,
+   * transposed, the row panel t2[p, :]) are copied in next to its (vv|vo)
+   * slice. Needs the factors (naux > 0) and host arrays, and implies the
+   * on-the-fly mode; t2 is borrowed until te_free. Results are bitwise those
+   * of the resident layout. */
+  int t2_host;
 } te_config;
 
 typedef struct te_stats {

@@ -217,8 +217,11 @@ static void stage(Job &J, const te_problem &P) {
   }
   stage_padded(J, P.t1, 1, 1, o, v, 1, o, vp, 1.0, J.t1);
 
-  // doubles: borrowed when already in device memory with an aligned v
-  if (dev && vp == v) {
+  // doubles: borrowed when already in device memory with an aligned v; left
+  // in host memory in the host-t2 mode (panels go to the slice cache)
+  if (J.t2h) {
+    J.t2 = nullptr;
+  } else if (dev && vp == v) {
     J.t2 = P.t2;
   } else {
     stage_padded(J, P.t2, o, o, v, v, o, vp, vp, 1.0, J.t2_own);
@@ -273,11 +276,12 @@ static void validate_device(Job &J, const te_problem &P) {
   chk(J.eo.p, J.eo.bytes / 8);
   chk(J.ev.p, J.ev.bytes / 8);
   chk(J.t1.p, J.t1.bytes / 8);
-  chk(J.t2, (size_t)J.o * J.o * J.vp * J.vp);
+  if (J.t2) chk(J.t2, (size_t)J.o * J.o * J.vp * J.vp);
   chk(J.K.p, J.K.bytes / 8);
   chk(J.In.p, J.In.bytes / 8);
   chk(J.X.p, J.X.bytes / 8);
-  HIPCHK(launch_t2_asym(J.t2, J.o, J.vp, (double *)(flag.as<char>() + 16), nullptr, J.s_main));
+  if (J.t2)
+    HIPCHK(launch_t2_asym(J.t2, J.o, J.vp, (double *)(flag.as<char>() + 16), nullptr, J.s_main));
   int bad = 0;
   double mm[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(&bad, flag.p, 4, hipMemcpyDeviceToHost, J.s_main));
@@ -323,9 +327,11 @@ const Operands &ensure_prec(Job &J, Prec p) {
     op.X = J.X.p; op.T2 = J.t2; op.In = J.In.p;
     op.xps = nX; op.tps = nT2; op.ips = nIn;
   } else if (p == Prec::F32) {
-    jalloc(J, op.T2_own, nT2 * 4);
+    if (J.t2) {    // (host t2: panels are converted as they enter the slice cache)
+      jalloc(J, op.T2_own, nT2 * 4);
+      HIPCHK(launch_to_f32(J.t2, op.T2_own.as<float>(), nT2, J.s_main));
+    }
     jalloc(J, op.In_own, nIn * 4);
-    HIPCHK(launch_to_f32(J.t2, op.T2_own.as<float>(), nT2, J.s_main));
     HIPCHK(launch_to_f32(J.In.as<double>(), op.In_own.as<float>(), nIn, J.s_main));
     if (nX) {
       jalloc(J, op.X_own, nX * 4);
@@ -338,13 +344,15 @@ const Operands &ensure_prec(Job &J, Prec p) {
     // the W build loads them as 16-byte chunks
     const int lo = (o + 7) / 8 * 8;
     const size_t nInP = (size_t)o * vp * o * lo, nT2T = (size_t)o * vp * vp * lo;
-    jalloc(J, op.T2_own, nT2 * 2 * 3);
     jalloc(J, op.In_own, nInP * 2 * 3);
-    jalloc(J, op.T2T_own, nT2T * 2 * 3);
-    HIPCHK(launch_to_bf16_parts(J.t2, op.T2_own.as<uint16_t>(), nT2, 3, J.s_main));
     HIPCHK(launch_in_bf16_parts(J.In.as<double>(), op.In_own.as<uint16_t>(), o, vp, lo, 3,
                                 J.s_main));
-    HIPCHK(launch_t2t_bf16_parts(J.t2, op.T2T_own.as<uint16_t>(), o, vp, lo, 3, J.s_main));
+    if (J.t2) {
+      jalloc(J, op.T2_own, nT2 * 2 * 3);
+      jalloc(J, op.T2T_own, nT2T * 2 * 3);
+      HIPCHK(launch_to_bf16_parts(J.t2, op.T2_own.as<uint16_t>(), nT2, 3, J.s_main));
+      HIPCHK(launch_t2t_bf16_parts(J.t2, op.T2T_own.as<uint16_t>(), o, vp, lo, 3, J.s_main));
+    }
     if (nX) {
       jalloc(J, op.X_own, nX * 2 * 3);
       HIPCHK(launch_to_bf16_parts(J.X.as<double>(), op.X_own.as<uint16_t>(), nX, 3, J.s_main));
@@ -503,6 +511,21 @@ static void assemble_slice(Job &J, Prec p, int occ, void *slot, double *tmp64, h
     HIPCHK(launch_to_bf16_parts(tmp64, (uint16_t *)slot, n, 3, s));
 }
 
+// Host t2: the column panel t2[:, occ] is gathered into the pinned bounce
+// buffer (once the previous copy out of it has completed), copied to the
+// device on stream s, and expanded by the panel kernel into a cache slot's
+// column panel and row panel / row form, in the precision the W build reads.
+static void fill_panels(Job &J, Prec p, int occ, char *col, char *row, hipStream_t s) {
+  const size_t o = J.o, v2 = (size_t)J.v * J.v;
+  HIPCHK(hipEventSynchronize(J.xc.pinned_free));
+  for (size_t l = 0; l < o; ++l)
+    std::memcpy(J.xc.pinned + l * v2, J.t2h + (l * o + (size_t)occ) * v2, v2 * 8);
+  HIPCHK(hipMemcpyAsync(J.xc.tstg.p, J.xc.pinned, o * v2 * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(J.xc.pinned_free, s));
+  const int lo = nparts(p) == 3 ? (J.o + 7) / 8 * 8 : J.o;
+  HIPCHK(launch_panel(p, J.xc.tstg.as<double>(), col, row, J.o, J.v, J.vp, lo, s));
+}
+
 std::vector<int> checked_triples(const Job &J, const int32_t *ijk, int64_t n) {
   if (n < 0 || (n > 0 && !ijk)) throw Fail(TE_EINVAL, "bad triple list");
   for (int64_t t = 0; t < n; ++t) {
@@ -511,6 +534,20 @@ std::vector<int> checked_triples(const Job &J, const int32_t *ijk, int64_t n) {
       throw Fail(TE_EINVAL, "triple " + std::to_string(t) + " is not 0<=i<=j<=k<o, not all equal");
   }
   return std::vector<int>(ijk, ijk + 3 * n);
+}
+
+void resident_t2_views(const Job &J, const Operands &op, Prec p, WItem &w) {
+  const size_t o = J.o, vp2 = (size_t)J.vp * J.vp, es = elem_size(p);
+  const int q[3] = {w.i, w.j, w.k};
+  for (int x = 0; x < 3; ++x) {
+    w.Tc[x] = (const char *)op.T2 + q[x] * vp2 * es;
+    w.Tr[x] = (const char *)op.T2 + q[x] * o * vp2 * es;
+    w.Tt[x] = op.T2T ? (const char *)op.T2T + q[x] * vp2 * op.lo * es : nullptr;
+  }
+  w.tcs = o * vp2;
+  w.trs = vp2;
+  w.tcps = op.tps;
+  w.t2tps = op.t2tps;
 }
 
 void resident_k_views(const Job &J, int i, int j, int k, EItem &e) {
@@ -584,17 +621,30 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
 
   Plan P;
   size_t slot_bytes = 0;
+  // a slot: the (vv|vo) slice, then (host t2) the column panel and the row
+  // panel (FP64, FP32) or row form (BF16 parts) of its occupied index
+  const size_t vp2 = (size_t)vp * vp;
+  const size_t x_bytes = vp3 * es * (size_t)nparts(p);
+  const size_t col_bytes = J.t2h ? (size_t)o * vp2 * es * nparts(p) : 0;
+  const size_t row_bytes =
+      J.t2h ? (nparts(p) == 3 ? vp2 * (size_t)op.lo * es * 3 : (size_t)o * vp2 * es) : 0;
   std::vector<int> after;   // slot contents once this call completes
   if (fly) {
-    slot_bytes = vp3 * es * (size_t)nparts(p);
+    slot_bytes = x_bytes + col_bytes + row_bytes;
     if (!J.xc.mem.p) {
       if (p != Prec::F64) J.xc.tmp64.alloc(vp3 * 8, &J.used, J.budget);
+      if (J.t2h) {
+        const size_t pb = (size_t)o * J.v * J.v * 8;
+        J.xc.tstg.alloc(pb, &J.used, J.budget);
+        HIPCHK(hipHostMalloc((void **)&J.xc.pinned, pb, hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&J.xc.pinned_free, hipEventDisableTiming));
+      }
       long room = (long)((J.budget - std::min(J.budget, J.used + ((size_t)1 << 28))) / slot_bytes);
       int S = J.x_cache ? J.x_cache : (int)std::min<long>(room, o);
       S = std::min(S, o);
       if (S < 3 || S > room) {
         J.xc.release();
-        throw Fail(TE_ENOMEM, "no room for three (vv|vo) slices of " +
+        throw Fail(TE_ENOMEM, "no room for three slice-cache slots of " +
                                   std::to_string(slot_bytes) + " bytes in the HBM budget");
       }
       J.xc.mem.alloc((size_t)S * slot_bytes, &J.used, J.budget);
@@ -631,9 +681,19 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
         w.Xs[2] = (const char *)op.X + (size_t)k * vp3 * es;
         w.xps = op.xps;
       }
-      w.T2 = op.T2; w.In = op.In; w.T2T = op.T2T;
-      w.tps = op.tps; w.ips = op.ips; w.t2tps = op.t2tps; w.lo = op.lo;
+      w.In = op.In;
+      w.ips = op.ips; w.lo = op.lo;
       w.W = W; w.o = o; w.vp = vp; w.i = i; w.j = j; w.k = k; w.mt = mt; w.nt = nt;
+      if (J.t2h) {
+        for (int d = 0; d < 3; ++d) {
+          const char *sb = J.xc.mem.as<char>() + (size_t)P.slot[pos][d] * slot_bytes;
+          w.Tc[d] = sb + x_bytes;
+          w.Tr[d] = w.Tt[d] = sb + x_bytes + col_bytes;
+        }
+        w.tcs = vp2; w.trs = vp2; w.tcps = (size_t)o * vp2; w.t2tps = vp2 * (size_t)op.lo;
+      } else {
+        resident_t2_views(J, op, p, w);
+      }
       EItem &e = ei[pos];
       if (fly) {
         const double *kb = kbuf.as<double>() + ((size_t)sl * B + q) * 3 * kblk;
@@ -674,9 +734,11 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
     // slices this batch needs: assembled on the W stream, after every earlier
     // W build (which may still read the slot being refilled)
     if (fly) HIPCHK(hipEventRecord(ta.start[b], J.s_aux));
-    for (auto &ld : P.loads[b])
-      assemble_slice(J, p, ld.first, J.xc.mem.as<char>() + (size_t)ld.second * slot_bytes,
-                     J.xc.tmp64.as<double>(), J.s_aux);
+    for (auto &ld : P.loads[b]) {
+      char *sb = J.xc.mem.as<char>() + (size_t)ld.second * slot_bytes;
+      assemble_slice(J, p, ld.first, sb, J.xc.tmp64.as<double>(), J.s_aux);
+      if (J.t2h) fill_panels(J, p, ld.first, sb + x_bytes, sb + x_bytes + col_bytes, J.s_aux);
+    }
     if (fly) HIPCHK(hipEventRecord(ta.stop[b], J.s_aux));
     HIPCHK(hipEventRecord(tw.start[b], J.s_aux));
     HIPCHK(launch_wbuild(p, witems.as<WItem>() + first, nullptr, cnt, tiles, (long)cnt * tiles,
@@ -762,6 +824,25 @@ Job::~Job() {
   }
   if (ev_start) (void)hipEventDestroy(ev_start);
   if (own_main && s_main) (void)hipStreamDestroy(s_main);
+  xc.release();
+}
+
+void Job::SliceCache::release() {
+  mem.release();
+  tmp64.release();
+  tstg.release();
+  held.clear();
+  S = 0;
+  pslot = -1;
+  if (pinned_free) {
+    (void)hipEventSynchronize(pinned_free);
+    (void)hipEventDestroy(pinned_free);
+    pinned_free = nullptr;
+  }
+  if (pinned) {
+    (void)hipHostFree(pinned);
+    pinned = nullptr;
+  }
 }
 
 static void check_problem(const te_problem *P) {
@@ -788,6 +869,25 @@ static void check_host_values(const te_problem &P) {
   const size_t o = P.o, v = P.v;
   if (!finite(P.eps_occ, o) || !finite(P.eps_vir, v) || !finite(P.t1, o * v))
     throw Fail(TE_EINVAL, "input holds a non-finite value");
+}
+
+// Host t2 (left in host memory): finite values and t_ij^ab = t_ji^ba, the
+// checks the device makes on a staged t2.
+static void check_host_t2(const te_problem &P) {
+  const size_t o = P.o, v = P.v, v2 = v * v;
+  double amax = 0.0, dmax = 0.0;
+  for (size_t i = 0; i < o; ++i)
+    for (size_t j = 0; j < o; ++j)
+      for (size_t a = 0; a < v; ++a)
+        for (size_t b = 0; b < v; ++b) {
+          const double x = P.t2[(i * o + j) * v2 + a * v + b];
+          if (!std::isfinite(x)) throw Fail(TE_EINVAL, "input holds a non-finite value");
+          amax = std::max(amax, std::abs(x));
+          dmax = std::max(dmax, std::abs(x - P.t2[(j * o + i) * v2 + b * v + a]));
+        }
+  if (dmax > 1e-12 * std::max(amax, 1e-300))
+    throw Fail(TE_EINVAL, "t2 is not pair-symmetric: max |t_ij^ab - t_ji^ba| = " +
+                              std::to_string(dmax));
 }
 
 int out_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
@@ -817,7 +917,15 @@ Job *make_job(const te_problem *P, const te_config *cfg_in, const JobOpts *opts)
   if (cfg_in) cfg = *cfg_in;
   if (cfg.x_mode < TE_X_AUTO || cfg.x_mode > TE_X_ON_THE_FLY)
     throw Fail(TE_EINVAL, "bad x_mode");
+  if (cfg.t2_host) {
+    if (P->naux == 0) throw Fail(TE_EINVAL, "t2 in host memory needs the factors (naux > 0)");
+    if (P->mem != TE_MEM_HOST) throw Fail(TE_EINVAL, "t2 in host memory needs host arrays");
+    if (cfg.x_mode == TE_X_RESIDENT)
+      throw Fail(TE_EINVAL, "t2 in host memory implies on-the-fly (vv|vo) slices");
+    if (opts) throw Fail(TE_EINVAL, "server jobs keep t2 on the device");
+  }
   if (cfg.validate) check_host_values(*P);
+  if (cfg.validate && cfg.t2_host) check_host_t2(*P);
   int ndev = 0;
   HIPCHK(hipGetDeviceCount(&ndev));
   if (cfg.device < 0 || cfg.device >= ndev) throw Fail(TE_EINVAL, "bad device ordinal");
@@ -859,8 +967,11 @@ Job *make_job(const te_problem *P, const te_config *cfg_in, const JobOpts *opts)
 
   const size_t o = J->o, vp = J->vp;
   const size_t xbytes = o * vp * vp * vp * 8;
+  if (cfg.t2_host) J->t2h = P->t2;
   if (P->naux == 0) {
     J->x_resident = true;
+  } else if (cfg.t2_host) {
+    J->x_resident = false;
   } else if (cfg.x_mode == TE_X_RESIDENT) {
     J->x_resident = true;
   } else if (cfg.x_mode == TE_X_ON_THE_FLY) {

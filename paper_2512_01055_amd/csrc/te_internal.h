@@ -23,13 +23,21 @@ enum class Prec : int { F64 = 0, F32 = 1, BF16X3 = 2, BF16X2 = 3 };
 struct WItem {
   const void *Xs[3];  // slices (ix|yf) for x in i, j, k: [vp][vp][vp] each;
                       // part p of slice q at Xs[q] + p * xps
-  const void *T2;  // t2,      layout [part][o][o][vp][vp]
+  // t2 reached through panels of the occupied indices q_0, q_1, q_2 = i, j, k
+  // (elements of the operand type; blocks are [vp][vp]):
+  //   column panel   block t2[p][q_x] at Tc[x] + p * tcs
+  //   row panel      block t2[q_x][l] at Tr[x] + l * trs   (FP64 / FP32 modes)
+  //   row form       t_{q_x l}^{yz}  at Tt[x] + (y vp + z) lo + l (BF16 modes)
+  // A resident t2 [part][o][o][vp][vp] gives tcs = o vp^2, trs = vp^2; panels
+  // copied into a cache slot give tcs = trs = vp^2. Part p of a column panel
+  // (or of the occupied segments' row panel) at + p * tcps, of the row form
+  // at + p * t2tps.
+  const void *Tc[3], *Tr[3], *Tt[3];
   const void *In;  // -(px|ql), layout [part][o][vp][o][lo]
-  const void *T2T; // BF16 modes: t2 with the occupied index last,
-                   // [part][o][vp*vp][lo], t2T[p][(y,z)][l] = t2[p][l][y][z]
-  size_t xps, tps, ips, t2tps;   // element stride between BF16 parts
-  int lo;          // length of the occupied rows of In and T2T: o in FP64 and
-                   // FP32 modes, o rounded up to 8 (zero padded) in BF16 modes
+  size_t xps, tcs, trs, tcps, ips, t2tps;
+  int lo;          // length of the occupied rows of In and the row form: o in
+                   // FP64 and FP32 modes, o rounded up to 8 (zero padded) in
+                   // BF16 modes
   void *W;         // three boxed W arrays of vp^3 each (FP64 or FP32)
   int o, vp, i, j, k;
   int mt, nt;      // tiles along M and N
@@ -97,6 +105,10 @@ hipError_t launch_to_bf16_parts(const double *src, uint16_t *dst, size_t n, int 
                                 hipStream_t s);
 // BF16 parts of t2 [o][o][vp][vp] regrouped as [part][o][vp*vp][lo] (occupied
 // index last, zero for l >= o).
+// Column panel and row panel (FP64, FP32) or row form (BF16 parts) of one
+// occupied index from its FP64 column panel [o][v][v]; see panel_kernel.
+hipError_t launch_panel(Prec p, const double *stg, void *col, void *row, int o, int v, int vp,
+                        int lo, hipStream_t s);
 hipError_t launch_t2t_bf16_parts(const double *t2, uint16_t *dst, int o, int vp, int lo,
                                  int nparts, hipStream_t s);
 // BF16 parts of In [o][vp][o][o] with the last index padded to lo.

@@ -92,7 +92,8 @@ struct Job {
   bool own_aux = true;         // false: no second stream / events (server jobs)
 
   DBuf eo, ev, t1, K, In, X, t2_own, sext;
-  const double *t2 = nullptr;
+  const double *t2 = nullptr;      // device t2 (padded), or null with t2 in host memory
+  const double *t2h = nullptr;     // host t2 [o][o][v][v] when it stays in host memory
   DBuf Bov_own, Boo_own, Bvv_own;
   const double *Bov = nullptr, *Boo = nullptr, *Bvv = nullptr;
   Operands op[4];
@@ -105,7 +106,12 @@ struct Job {
     size_t slot_bytes = 0;
     DBuf mem, tmp64;
     std::vector<int> held;
-    void release() { mem.release(); tmp64.release(); held.clear(); S = 0; pslot = -1; }
+    // host t2: FP64 column panel on the device, its pinned host bounce
+    // buffer, and the event after which the bounce buffer may be refilled
+    DBuf tstg;
+    double *pinned = nullptr;
+    hipEvent_t pinned_free = nullptr;
+    void release();
   } xc;
   int nT = 0, nsext = 0;
   ~Job();
@@ -126,6 +132,9 @@ size_t job_footprint(int o, int v, int naux, Prec p);
 int out_bytes(Prec p);
 const Operands &ensure_prec(Job &J, Prec p);
 void resident_k_views(const Job &J, int i, int j, int k, EItem &e);
+// t2 views of a W item over the device-resident t2 (and row form) of `op`;
+// w.i, w.j, w.k must be set.
+void resident_t2_views(const Job &J, const Operands &op, Prec p, WItem &w);
 // Optional E[4] / E[5] outputs of run_triples (any pointer may be null).
 struct SplitOut {
   double *e4_sum = nullptr, *e5_sum = nullptr;   // sums over the listed triples

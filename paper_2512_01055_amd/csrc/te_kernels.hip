@@ -279,6 +279,52 @@ __device__ inline void split_store(double r, uint16_t *dst, size_t q, size_t n, 
   }
 }
 
+// Panels of one occupied index p for a slice-cache slot, from its FP64
+// column panel stg[l][a][b] = t2[l][p][a][b] (unpadded v, as copied from host
+// memory), in the operand type of the W build and padded to vp like the
+// resident arrays (same conversions, so the same bits):
+//   col[part][l][a][b]      = t2[l][p][a][b]
+//   row[l][a][b]            = t2[p][l][a][b] = stg[l][b][a]        (FP64, FP32)
+//   row[part][y vp + z][l]  = t2[p][l][y][z] = stg[l][z][y], l < lo (BF16 parts)
+__device__ inline void put(double *d, size_t q, size_t, double x, int) { d[q] = x; }
+__device__ inline void put(float *d, size_t q, size_t, double x, int) { d[q] = (float)x; }
+__device__ inline void put(uint16_t *d, size_t q, size_t n, double x, int np) {
+  split_store(x, d, q, n, np);
+}
+
+template <typename OT>
+__global__ void panel_kernel(const double *__restrict__ stg, OT *__restrict__ col,
+                             OT *__restrict__ row, int o, int v, int vp, int lo, int nparts) {
+  constexpr bool form = sizeof(OT) == 2;
+  const long vp2 = (long)vp * vp;
+  const size_t ncol = (size_t)o * vp2;
+  const size_t nrow = form ? (size_t)vp2 * lo : ncol;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < ncol + nrow;
+       q += (size_t)gridDim.x * blockDim.x) {
+    if (q < ncol) {
+      const int b = (int)(q % vp);
+      const size_t r = q / vp;
+      const int a = (int)(r % vp), l = (int)(r / vp);
+      const double x = (a < v && b < v) ? stg[((size_t)l * v + a) * v + b] : 0.0;
+      put(col, q, ncol, x, nparts);
+    } else if (form) {
+      const size_t qq = q - ncol;
+      const int l = (int)(qq % lo);
+      const long pair = (long)(qq / lo);
+      const int y = (int)(pair / vp), z = (int)(pair % vp);
+      const double x = (l < o && y < v && z < v) ? stg[((size_t)l * v + z) * v + y] : 0.0;
+      put(row, qq, nrow, x, nparts);
+    } else {
+      const size_t qq = q - ncol;
+      const int b = (int)(qq % vp);
+      const size_t r = qq / vp;
+      const int a = (int)(r % vp), l = (int)(r / vp);
+      const double x = (a < v && b < v) ? stg[((size_t)l * v + b) * v + a] : 0.0;
+      put(row, qq, nrow, x, nparts);
+    }
+  }
+}
+
 __global__ void t2t_bf16_kernel(const double *__restrict__ t2, uint16_t *__restrict__ dst, int o,
                                 int vp, int lo, int nparts) {
   const long vp2 = (long)vp * vp;
@@ -448,6 +494,23 @@ hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t s)
 hipError_t launch_to_bf16_parts(const double *src, uint16_t *dst, size_t n, int nparts,
                                 hipStream_t s) {
   to_bf16_parts_kernel<<<blocks_for(n), WG, 0, s>>>(src, dst, n, nparts);
+  return hipGetLastError();
+}
+
+hipError_t launch_panel(Prec p, const double *stg, void *col, void *row, int o, int v, int vp,
+                        int lo, hipStream_t s) {
+  const size_t ncol = (size_t)o * vp * vp;
+  const bool split = p == Prec::BF16X3 || p == Prec::BF16X2;
+  const size_t n = ncol + (split ? (size_t)vp * vp * lo : ncol);
+  if (p == Prec::F64)
+    panel_kernel<double><<<blocks_for(n), WG, 0, s>>>(stg, (double *)col, (double *)row, o, v,
+                                                      vp, lo, 1);
+  else if (p == Prec::F32)
+    panel_kernel<float><<<blocks_for(n), WG, 0, s>>>(stg, (float *)col, (float *)row, o, v, vp,
+                                                     lo, 1);
+  else
+    panel_kernel<uint16_t><<<blocks_for(n), WG, 0, s>>>(stg, (uint16_t *)col, (uint16_t *)row,
+                                                        o, v, vp, lo, 3);
   return hipGetLastError();
 }
 

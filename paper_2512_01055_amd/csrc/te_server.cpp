@@ -318,9 +318,10 @@ ServerImpl::Launch ServerImpl::launch_round() {
     w.Xs[0] = (const char *)op.X + (size_t)i * vp3 * es;
     w.Xs[1] = (const char *)op.X + (size_t)jj * vp3 * es;
     w.Xs[2] = (const char *)op.X + (size_t)k * vp3 * es;
-    w.T2 = op.T2; w.In = op.In; w.T2T = op.T2T;
-    w.xps = op.xps; w.tps = op.tps; w.ips = op.ips; w.t2tps = op.t2tps; w.lo = op.lo;
+    w.In = op.In;
+    w.xps = op.xps; w.ips = op.ips; w.lo = op.lo;
     w.W = W; w.o = J.o; w.vp = (int)vp; w.i = i; w.j = jj; w.k = k;
+    resident_t2_views(J, op, P, w);
     w.mt = (int)((vp * vp + bm - 1) / bm);
     w.nt = (int)((vp + 16 * nb - 1) / (16 * nb));
     const long nt_ = 3L * w.mt * w.nt;

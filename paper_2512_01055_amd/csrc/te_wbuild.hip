@@ -23,10 +23,13 @@ namespace {
 // These are the twelve terms of Eq. 2 under the six permutations of Eq. 5,
 // grouped by the index that is not paired with another virtual index. The
 // three results are written to separate boxed arrays; W is their sum.
+// Occupied indices are named by value (tq, ix, iy) where they select a row,
+// and by position in (i, j, k) (xa, tr, op) where they select a slice or a
+// t2 panel.
 struct Setup {
   int xa[2];      // X slice (0: X_i, 1: X_j, 2: X_k) of segments 0/1 (seg 1 transposed)
-  int tq[2], tr[2];  // T_{tq tr} rows for the B side of segments 0/1
-  int op[2], om[2];  // occupied-term A side: om 0 -> t2[op][l], 1 -> t2[l][op]
+  int tq[2], tr[2];  // T_{tq tr} rows for the B side of segments 0/1 (tr: position)
+  int op[2], om[2];  // occupied-term A side (op: position): om 0 -> t2[op][l], 1 -> t2[l][op]
   int ix[2], iy[2];  // In_{ix iy} rows for segments 2/3
 };
 
@@ -34,18 +37,18 @@ __device__ inline Setup make_setup(int g, int i, int j, int k) {
   Setup s;
   if (g == 0) {
     s.xa[0] = 0; s.xa[1] = 1;
-    s.tq[0] = k; s.tr[0] = j; s.tq[1] = k; s.tr[1] = i;
-    s.op[0] = i; s.om[0] = 0; s.op[1] = j; s.om[1] = 1;
+    s.tq[0] = k; s.tr[0] = 1; s.tq[1] = k; s.tr[1] = 0;
+    s.op[0] = 0; s.om[0] = 0; s.op[1] = 1; s.om[1] = 1;
     s.ix[0] = k; s.iy[0] = j; s.ix[1] = k; s.iy[1] = i;
   } else if (g == 1) {
     s.xa[0] = 1; s.xa[1] = 2;
-    s.tq[0] = i; s.tr[0] = k; s.tq[1] = i; s.tr[1] = j;
-    s.op[0] = k; s.om[0] = 1; s.op[1] = j; s.om[1] = 0;
+    s.tq[0] = i; s.tr[0] = 2; s.tq[1] = i; s.tr[1] = 1;
+    s.op[0] = 2; s.om[0] = 1; s.op[1] = 1; s.om[1] = 0;
     s.ix[0] = i; s.iy[0] = j; s.ix[1] = i; s.iy[1] = k;
   } else {
     s.xa[0] = 0; s.xa[1] = 2;
-    s.tq[0] = j; s.tr[0] = k; s.tq[1] = j; s.tr[1] = i;
-    s.op[0] = k; s.om[0] = 1; s.op[1] = i; s.om[1] = 0;
+    s.tq[0] = j; s.tr[0] = 2; s.tq[1] = j; s.tr[1] = 0;
+    s.op[0] = 2; s.om[0] = 1; s.op[1] = 0; s.om[1] = 0;
     s.ix[0] = j; s.iy[0] = i; s.ix[1] = j; s.iy[1] = k;
   }
   return s;
@@ -103,8 +106,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
   const Setup su = make_setup(g, w.i, w.j, w.k);
   const T *XA0 = reinterpret_cast<const T *>(w.Xs[su.xa[0]]);
   const T *XA1 = reinterpret_cast<const T *>(w.Xs[su.xa[1]]);
-  const T *T2 = reinterpret_cast<const T *>(w.T2);
   const T *In = reinterpret_cast<const T *>(w.In);
+  // t2 through the panels of i, j, k: T_{tq tr} rows of the X segments, and
+  // the occupied segments' t2[op][l] (row panel) or t2[l][op] (column panel)
+  const T *TB0 = reinterpret_cast<const T *>(w.Tc[su.tr[0]]) + (long)su.tq[0] * w.tcs;
+  const T *TB1 = reinterpret_cast<const T *>(w.Tc[su.tr[1]]) + (long)su.tq[1] * w.tcs;
 
   // --- per-thread row pointers for the X phase
   long rowA[CA][2];
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
     rowA[u][0] = mm * vp;
     rowA[u][1] = (my * vp + mx) * vp;
   }
-  long rowB[CB][2];
+  long rowB[CB];
   long rowI[CB][2];
   int kcB[CB];
   bool okB[CB];
@@ -134,19 +140,20 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
     int n = n0 + row;
     okB[u] = (c < BN * CPR) && (n < vp);
     long nn = okB[u] ? n : 0;
-    rowB[u][0] = (((long)su.tq[0] * o + su.tr[0]) * vp + nn) * vp;
-    rowB[u][1] = (((long)su.tq[1] * o + su.tr[1]) * vp + nn) * vp;
+    rowB[u] = nn * vp;
   }
-  long baseO[2], ksO[2];
+  const T *TO[2];
+  long ksO[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    if (su.om[s] == 0) { baseO[s] = (long)su.op[s] * o * vp2; ksO[s] = vp2; }
-    else               { baseO[s] = (long)su.op[s] * vp2;     ksO[s] = (long)o * vp2; }
+    if (su.om[s] == 0) { TO[s] = reinterpret_cast<const T *>(w.Tr[su.op[s]]); ksO[s] = (long)w.trs; }
+    else               { TO[s] = reinterpret_cast<const T *>(w.Tc[su.op[s]]); ksO[s] = (long)w.tcs; }
   }
   // BF16 modes: occupied-segment rows of T2T (t_{p l}^{yz} with l last), read
   // like the X rows; om = 1 takes the swapped pair (t_{l p}^{yz} = t_{p l}^{zy})
   const int lo = w.lo;
-  const T *T2T = reinterpret_cast<const T *>(w.T2T);
+  const T *TT0 = reinterpret_cast<const T *>(w.Tt[su.op[0]]);
+  const T *TT1 = reinterpret_cast<const T *>(w.Tt[su.op[1]]);
   long rowO[TR::SPLIT ? CA : 1][2];
   if constexpr (TR::SPLIT) {
 #pragma unroll
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
       long mx = mm / vp, my = mm - mx * vp;
 #pragma unroll
       for (int s = 0; s < 2; ++s)
-        rowO[u][s] = ((long)su.op[s] * vp2 + (su.om[s] ? my * vp + mx : mm)) * lo;
+        rowO[u][s] = (su.om[s] ? my * vp + mx : mm) * lo;
     }
   }
 #pragma unroll
@@ -193,10 +200,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
         int kg = kb + kcB[u];
         bool ok = okB[u] && kg < KX;
         int seg = kg >= vp;
-        long off = rowB[u][seg] + (kg - seg * vp);
+        long off = rowB[u] + (kg - seg * vp);
+        const T *tb = seg ? TB1 : TB0;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-          if (ok) rb[u][p].load(T2 + p * w.tps + off); else rb[u][p].zero();
+          if (ok) rb[u][p].load(tb + p * w.tcps + off); else rb[u][p].zero();
         }
       }
     } else if constexpr (TR::SPLIT) {
@@ -208,9 +216,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
         bool ok = okA[u] && kg < KO;
         int seg = kg >= lo;
         long off = rowO[u][seg] + (kg - seg * lo);
+        const T *tt = seg ? TT1 : TT0;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-          if (ok) ra[u][p].load(T2T + p * w.t2tps + off); else ra[u][p].zero();
+          if (ok) ra[u][p].load(tt + p * w.t2tps + off); else ra[u][p].zero();
         }
       }
 #pragma unroll
@@ -237,10 +246,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
         long m = m0 + mc;
         bool ok = (c < BM * CPR) && kg < KO && m < M;
         int seg = kg >= o;
-        long off = baseO[seg] + (long)(kg - seg * o) * ksO[seg] + m;
+        long off = (long)(kg - seg * o) * ksO[seg] + m;
+        const T *to = seg ? TO[1] : TO[0];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-          if (ok) ra[u][p].load(T2 + p * w.tps + off); else ra[u][p].zero();
+          if (ok) ra[u][p].load(to + p * w.tcps + off); else ra[u][p].zero();
         }
       }
 #pragma unroll

@@ -37,7 +37,8 @@ class Problem(C.Structure):
 
 class Config(C.Structure):
     _fields_ = [("device", C.c_int), ("stream", C.c_void_p), ("hbm_budget", C.c_size_t),
-                ("validate", C.c_int), ("x_mode", C.c_int), ("x_cache_slices", C.c_int)]
+                ("validate", C.c_int), ("x_mode", C.c_int), ("x_cache_slices", C.c_int),
+                ("t2_host", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -188,19 +189,19 @@ class Job:
 
     def __init__(self, prob, *, device: int = 0, stream=None, hbm_budget: int = 0,
                  validate: bool = False, x_mode: str = "auto", x_cache_slices: int = 0,
-                 explicit: bool = False):
+                 explicit: bool = False, t2_host: bool = False):
         L = lib()
         o, v = int(prob.o), int(prob.v)
         naux = 0 if explicit else int(prob.naux)
         self.o, self.v, self.naux = o, v, naux
         self._p, self._arrays = make_problem_struct(prob, o, v, naux)
         cfg = Config(device, _stream_handle(stream), hbm_budget, int(validate),
-                     X_MODES[x_mode], x_cache_slices)
+                     X_MODES[x_mode], x_cache_slices, int(t2_host))
         h = C.c_void_p()
         _check(L.te_init(C.byref(self._p), C.byref(cfg), C.byref(h)))
         self._h = h
-        if not self._arrays.device:
-            self._arrays = None      # host arrays were copied
+        if not self._arrays.device and not t2_host:
+            self._arrays = None      # host arrays were copied (a host t2 is borrowed)
 
     @property
     def n_triples(self) -> int:

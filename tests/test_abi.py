@@ -69,6 +69,17 @@ def test_argument_errors_need_no_device():
     assert lib.te_init(C.byref(p), None, C.byref(h)) == te.EINVAL   # explicit ints missing
     p.naux = -1
     assert lib.te_init(C.byref(p), None, C.byref(h)) == te.EINVAL
+    # t2 in host memory: needs the factors, host arrays, and no resident slices
+    p.naux = 3
+    p.B_vv = x.ctypes.data
+    for mem, naux, xmode in ((0, 0, 0), (1, 3, 0), (0, 3, 1)):
+        p.mem, p.naux = mem, naux
+        if naux == 0:
+            for n in ("ovvv", "ovoo", "ovov"):
+                setattr(p, n, x.ctypes.data)
+        cfg = te.Config(0, None, 0, 0, xmode, 0, 1)
+        assert lib.te_init(C.byref(p), C.byref(cfg), C.byref(h)) == te.EINVAL
+        assert b"t2 in host memory" in lib.te_last_error()
     e = C.c_double()
     assert lib.te_energy(None, 0, C.byref(e), None, None) == te.EINVAL
     assert lib.te_free(None) == te.EINVAL

@@ -364,3 +364,28 @@ def test_checkpointed_run_resumes_to_the_same_bits(tmp_path):
         with pytest.raises(te.TeError) as ei:
             job.energy_checkpointed("fp64", b, chunk=9, tag=8)
         assert ei.value.status == te.EINVAL and os.path.getsize(b) == size
+
+
+@pytest.mark.parametrize("shape", [(9, 48, 40, 28, 3), (7, 61, 30, 18, 5)], ids=["o9v48", "o7v61"])
+def test_host_t2_panels_equal_resident(shape):
+    """t2 left in host memory, its panels copied into the slice cache as slots
+    fill: every precision gives the resident layout's per-triple values
+    bitwise (small caches, so panels are evicted and copied again)."""
+    o, v, naux, seed, slices = shape
+    te = _te()
+    P = make_problem(o, v, naux, seed)
+    ref = {}
+    with te.Job(P, device=0, x_mode="resident") as job:
+        for prec in PRECS:
+            ref[prec] = job.energy(prec, per_triple=True)[2]
+    sub = sample_triples(o, 8, 3)
+    allt = te.triple_list(o)
+    idx = [int(np.nonzero((allt == s_).all(1))[0][0]) for s_ in sub]
+    with te.Job(P, device=0, t2_host=True, x_cache_slices=slices, validate=True) as job:
+        for prec in PRECS:
+            print(f"\n[host t2 o={o} v={v} prec={prec}]", flush=True)
+            E, st, pt = job.energy(prec, per_triple=True)
+            assert np.array_equal(pt, ref[prec]), prec
+            assert st["slices_assembled"] > o
+            _, ps, _ = job.energy_triples(sub, prec)
+            assert np.array_equal(ps, ref[prec][idx])
