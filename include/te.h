@@ -108,7 +108,9 @@ typedef struct te_stats {
   double flops;          /* algorithmic W flops: n_triples * 12 v^3 (v + o)      */
   double tflops;         /* flops / seconds / 1e12                               */
   int64_t n_triples;     /* occupied triples evaluated                           */
-  double stage_seconds;  /* part of `seconds` spent preparing operands           */
+  double stage_seconds;  /* part of `seconds` before the first launch: operand
+                            conversion, scratch and slice-cache allocation,
+                            planning (one-off set-up, not per triple)           */
   double assemble_flops; /* on-the-fly mode: flops spent assembling (vv|vo)
                             slices and per-triple (ov|ov) blocks               */
   /* Device time of the kernels, from HIP events recorded around each launch
