@@ -67,13 +67,24 @@ __global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ it
   const WT *W0 = reinterpret_cast<const WT *>(e.W);
   const WT *W1 = W0 + vp3;
   const WT *W2 = W1 + vp3;
-  for (int idx = tid; idx < 6 * BOX3; idx += WG) {
-    int s = idx >> 9;
-    if (canon[s] != s) continue;
-    int r = idx & (BOX3 - 1);
-    long base = ((((long)bx[s][0] * nT + bx[s][1]) * nT + bx[s][2]) << 9) + r;
-    double wv = ((double)gld(W0 + base) + (double)gld(W1 + base)) + (double)gld(W2 + base);
-    box[s * BX_S + bxi(r >> 6, (r >> 3) & 7, r & 7)] = wv;
+  // every load of the thread is issued before the first LDS store (one
+  // memory latency per workgroup, not one per element); element u of the
+  // thread is element tid + 256 (u % 2) of slot u / 2
+  constexpr int PER = 6 * BOX3 / WG;
+  double wv[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int s = u >> 1, r = tid + WG * (u & 1);
+    wv[u] = 0.0;
+    if (canon[s] == s) {
+      const long base = ((((long)bx[s][0] * nT + bx[s][1]) * nT + bx[s][2]) << 9) + r;
+      wv[u] = ((double)gld(W0 + base) + (double)gld(W1 + base)) + (double)gld(W2 + base);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int s = u >> 1, r = tid + WG * (u & 1);
+    if (canon[s] == s) box[s * BX_S + bxi(r >> 6, (r >> 3) & 7, r & 7)] = wv[u];
   }
   __syncthreads();
 
