@@ -25,8 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "(T) TFLOP/s at o=40,v=400 FP64 vs FP32/split; jobs/s + p99; |dE| vs FP64"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
-ISSUED = {"fp64": 1, "fp32": 1, "bf16x3": 6, "bf16x2": 3}   # MFMA products per algorithmic one
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0, "fp16x2": 2500.0}
+ISSUED = {"fp64": 1, "fp32": 1, "bf16x3": 6, "bf16x2": 3, "fp16x2": 3}   # MFMA products per algorithmic one
 
 
 def log(msg: str) -> None:
@@ -245,7 +245,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16x2")
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16x2,fp16x2")
     ap.add_argument("--o", type=int, default=40)
     ap.add_argument("--v", type=int, default=400)
     ap.add_argument("--naux", type=int, default=1200)
@@ -371,7 +371,8 @@ def main() -> int:
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(r["ms_per_step"], 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x2": "bf16x2"}[head],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x2": "bf16x2",
+                  "fp16x2": "fp16x2"}[head],
         "data": "synthetic",
         "config": {"workload": f"(T) of closed-shell CCSD(T), o={o} v={v} naux={naux}, "
                                f"seeded synthetic DF factors and MP2-like amplitudes (seed {seed}), "
@@ -384,7 +385,7 @@ def main() -> int:
                      "traffic_unit": "bytes/launch",
                      "kernel": f"wbuild_kernel<{head}>",
                      "avg_launch_ms": round(r["w_kernel_avg_ms"], 4),
-                     "sustained_mfma_tflops": round(te.mfma_sustained(head if head != "bf16x2" else "bf16x3", 2.0), 2)},
+                     "sustained_mfma_tflops": round(te.mfma_sustained(head if head in ("fp64", "fp32", "bf16x3") else "bf16x3", 2.0), 2)},
     }
     precs_out = {}
     for p_, rr in results.items():

@@ -48,7 +48,10 @@ typedef enum te_precision {
   TE_FP32 = 1,    /* operands rounded to FP32, FP32 MFMA, FP32 accumulation    */
   TE_BF16X3 = 2,  /* operands split into 3 BF16 parts, 6 cross products,
                      FP32 accumulation                                         */
-  TE_BF16X2 = 3   /* 2 BF16 parts, 3 cross products, FP32 accumulation         */
+  TE_BF16X2 = 3,  /* 2 BF16 parts, 3 cross products, FP32 accumulation         */
+  TE_FP16X2 = 4   /* operands scaled by a power of two per operand family and
+                     split into 2 FP16 parts, 3 cross products, FP32
+                     accumulation, unscaled at the end (not with t2_host)      */
 } te_precision;
 
 typedef enum te_memkind { TE_MEM_HOST = 0, TE_MEM_DEVICE = 1 } te_memkind;

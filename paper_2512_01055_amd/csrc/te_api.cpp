@@ -154,7 +154,9 @@ std::vector<int> sextet_list(int nT) {
 static size_t elem_size(Prec p) {
   return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2);
 }
-static int nparts(Prec p) { return p == Prec::BF16X3 || p == Prec::BF16X2 ? 3 : 1; }
+static int nparts(Prec p) {
+  return p == Prec::BF16X3 || p == Prec::BF16X2 ? 3 : (p == Prec::FP16X2 ? 2 : 1);
+}
 static size_t out_size(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
 // ------------------------------------------------------------ staging
@@ -180,6 +182,38 @@ static void stage_padded(Job &J, const double *src, int d0, int d1, int d2, int 
   const double *s = device_view(J, src, (size_t)d0 * d1 * d2 * d3, tmp);
   HIPCHK(launch_pad4(s, dst.as<double>(), d0, d1, d2, d3, p1, p2, p3, scale, J.s_main));
   if (tmp.p) HIPCHK(hipStreamSynchronize(J.s_main));
+}
+
+// Largest |x| over n device doubles, and the largest column norm^2 of a
+// factor [naux][ncol]; both synchronous (set-up only).
+static double read_max(Job &J, DBuf &m) {
+  unsigned long long bits = 0;
+  HIPCHK(hipMemcpyAsync(&bits, m.p, 8, hipMemcpyDeviceToHost, J.s_main));
+  HIPCHK(hipStreamSynchronize(J.s_main));
+  double r;
+  std::memcpy(&r, &bits, 8);
+  return r;
+}
+static double dev_absmax(Job &J, const double *x, size_t n) {
+  if (!x || !n) return 0.0;
+  DBuf m;
+  m.alloc(8, nullptr, 0);
+  HIPCHK(hipMemsetAsync(m.p, 0, 8, J.s_main));
+  HIPCHK(launch_absmax(x, n, m.as<unsigned long long>(), J.s_main));
+  return read_max(J, m);
+}
+static double dev_colnorm_max(Job &J, const double *B, long ncol) {
+  if (!B || ncol <= 0) return 0.0;
+  DBuf m;
+  m.alloc(8, nullptr, 0);
+  HIPCHK(hipMemsetAsync(m.p, 0, 8, J.s_main));
+  HIPCHK(launch_colnorm_max(B, J.naux, ncol, m.as<unsigned long long>(), J.s_main));
+  return read_max(J, m);
+}
+// 2^k with k the largest integer such that 2^k m <= 2^14 (1 for m = 0)
+static double pow2_scale(double m) {
+  if (!(m > 0.0) || !std::isfinite(m)) return 1.0;
+  return std::ldexp(1.0, (int)std::floor(std::log2(16384.0 / m)));
 }
 
 static void gemm_stage(Job &J, const double *A, long lda, const double *B, long ldb, int M,
@@ -235,6 +269,9 @@ static void stage(Job &J, const te_problem &P) {
     J.Bov = device_view(J, P.B_ov, (size_t)naux * o * v, J.Bov_own);
     J.Boo = device_view(J, P.B_oo, (size_t)naux * o * o, J.Boo_own);
     J.Bvv = device_view(J, P.B_vv, (size_t)naux * v * v, J.Bvv_own);
+    // |(px|yf)| <= |B_px| |B_yf| (Cauchy-Schwarz over the factor index)
+    J.x_bound = std::sqrt(dev_colnorm_max(J, J.Bov, (long)o * v) *
+                          dev_colnorm_max(J, J.Bvv, (long)v * v));
     // K[p][x][q][y] = (px|qy), for V (Eq. 3); when (vv|vo) is assembled on
     // the fly the three blocks a triple reads are assembled with it instead
     if (J.x_resident) {
@@ -302,6 +339,8 @@ static void drop_operands(Operands &op) {
   op.X = op.T2 = op.In = op.T2T = nullptr;
   op.xps = op.tps = op.ips = op.t2tps = 0;
   op.lo = 0;
+  op.scale = 1.0f;
+  op.sigma_x = op.sigma_t = 1.0;
 }
 
 const Operands &ensure_prec(Job &J, Prec p) {
@@ -313,7 +352,8 @@ const Operands &ensure_prec(Job &J, Prec p) {
   if (p != Prec::F64) {
     HIPCHK(hipStreamSynchronize(J.s_main));
     if (J.s_aux) HIPCHK(hipStreamSynchronize(J.s_aux));
-    drop_operands(J.op[slot == (int)Prec::F32 ? (int)Prec::BF16X3 : (int)Prec::F32]);
+    for (int q : {(int)Prec::F32, (int)Prec::BF16X3, (int)Prec::FP16X2})
+      if (q != slot) drop_operands(J.op[q]);
   }
   const int o = J.o, vp = J.vp;
   const size_t nT2 = (size_t)o * o * vp * vp;
@@ -340,6 +380,39 @@ const Operands &ensure_prec(Job &J, Prec p) {
     }
     op.X = op.X_own.p; op.T2 = op.T2_own.p; op.In = op.In_own.p;
     op.xps = nX; op.tps = nT2; op.ips = nIn;
+  } else if (p == Prec::FP16X2) {
+    // two FP16 parts of sigma x; sigma_x scales X and In (their products with
+    // t2 share one accumulator), sigma_t scales t2, each bringing the largest
+    // magnitude to at most 2^14 (FP16 holds up to 65504)
+    if (!J.t2) throw Fail(TE_EINVAL, "FP16 parts need t2 in device memory");
+    const int lo = (o + 7) / 8 * 8;
+    const size_t nInP = (size_t)o * vp * o * lo, nT2T = (size_t)o * vp * vp * lo;
+    double mx = dev_absmax(J, J.In.as<double>(), nIn);
+    if (J.naux > 0) {
+      // the factor bound, the same whether the slices are resident or
+      // assembled on the fly
+      mx = std::max(mx, J.x_bound);
+    } else {
+      mx = std::max(mx, dev_absmax(J, J.X.as<double>(), nX));
+    }
+    op.sigma_x = pow2_scale(mx);
+    op.sigma_t = pow2_scale(dev_absmax(J, J.t2, nT2));
+    op.scale = (float)(1.0 / (op.sigma_x * op.sigma_t));
+    jalloc(J, op.T2_own, nT2 * 2 * 2);
+    jalloc(J, op.In_own, nInP * 2 * 2);
+    jalloc(J, op.T2T_own, nT2T * 2 * 2);
+    HIPCHK(launch_to_f16_parts(J.t2, op.T2_own.as<uint16_t>(), nT2, op.sigma_t, J.s_main));
+    HIPCHK(launch_in_f16_parts(J.In.as<double>(), op.In_own.as<uint16_t>(), o, vp, lo,
+                               op.sigma_x, J.s_main));
+    HIPCHK(launch_t2t_f16_parts(J.t2, op.T2T_own.as<uint16_t>(), o, vp, lo, op.sigma_t,
+                                J.s_main));
+    if (nX) {
+      jalloc(J, op.X_own, nX * 2 * 2);
+      HIPCHK(launch_to_f16_parts(J.X.as<double>(), op.X_own.as<uint16_t>(), nX, op.sigma_x,
+                                 J.s_main));
+    }
+    op.X = op.X_own.p; op.T2 = op.T2_own.p; op.In = op.In_own.p; op.T2T = op.T2T_own.p;
+    op.xps = nX; op.tps = nT2; op.ips = nInP; op.t2tps = nT2T; op.lo = lo;
   } else {
     // BF16 parts; the occupied-index operands get l last and padded to 8 so
     // the W build loads them as 16-byte chunks
@@ -510,6 +583,8 @@ static void assemble_slice(Job &J, Prec p, int occ, void *slot, double *tmp64, h
   if (p == Prec::F32) HIPCHK(launch_to_f32(tmp64, (float *)slot, n, s));
   if (p == Prec::BF16X3 || p == Prec::BF16X2)
     HIPCHK(launch_to_bf16_parts(tmp64, (uint16_t *)slot, n, 3, s));
+  if (p == Prec::FP16X2)
+    HIPCHK(launch_to_f16_parts(tmp64, (uint16_t *)slot, n, J.op[(int)Prec::FP16X2].sigma_x, s));
 }
 
 // Host t2: the column panel t2[:, occ] is gathered into the pinned bounce
@@ -690,7 +765,7 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
         w.xps = op.xps;
       }
       w.In = op.In;
-      w.ips = op.ips; w.lo = op.lo;
+      w.ips = op.ips; w.lo = op.lo; w.scale = op.scale;
       w.W = W; w.o = o; w.vp = vp; w.i = i; w.j = j; w.k = k; w.mt = mt; w.nt = nt;
       if (J.t2h) {
         for (int d = 0; d < 3; ++d) {
@@ -916,9 +991,9 @@ size_t job_footprint(int o, int v, int naux, Prec p) {
   const size_t nX = O * VP * VP * VP, nT2 = O * O * VP * VP, nIn = O * VP * O * O;
   b += 8 * nX;
   if (p == Prec::F32) b += 4 * (nX + nT2 + nIn);
-  if (p == Prec::BF16X3 || p == Prec::BF16X2) {
+  if (p == Prec::BF16X3 || p == Prec::BF16X2 || p == Prec::FP16X2) {
     const size_t LO = (O + 7) / 8 * 8;
-    b += 6 * (nX + nT2 + O * VP * O * LO + O * VP * VP * LO);
+    b += (p == Prec::FP16X2 ? 4 : 6) * (nX + nT2 + O * VP * O * LO + O * VP * VP * LO);
   }
   return b + 32 * 256;
 }

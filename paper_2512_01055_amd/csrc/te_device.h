@@ -14,6 +14,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int WG = 256;
@@ -42,22 +43,29 @@ template <Prec P> struct Tr;
 template <> struct Tr<Prec::F64> {
   using T = double; using Acc = d4; using Out = double;
   static constexpr int KT = 16, PAD = 0, NP = 1, KM = 4, ROWQ = 1;
-  static constexpr bool SPLIT = false;
+  static constexpr bool SPLIT = false, SCALED = false;
 };
 template <> struct Tr<Prec::F32> {
   using T = float; using Acc = f4; using Out = float;
   static constexpr int KT = 32, PAD = 0, NP = 1, KM = 4, ROWQ = 4;
-  static constexpr bool SPLIT = false;
+  static constexpr bool SPLIT = false, SCALED = false;
 };
 template <> struct Tr<Prec::BF16X3> {
-  using T = uint16_t; using Acc = f4; using Out = float;
+  using T = uint16_t; using Acc = f4; using Out = float; using Frag = bf8;
   static constexpr int KT = 32, PAD = 0, NP = 3, KM = 32, ROWQ = 4;
-  static constexpr bool SPLIT = true;
+  static constexpr bool SPLIT = true, SCALED = false;
 };
 template <> struct Tr<Prec::BF16X2> {
-  using T = uint16_t; using Acc = f4; using Out = float;
+  using T = uint16_t; using Acc = f4; using Out = float; using Frag = bf8;
   static constexpr int KT = 32, PAD = 0, NP = 2, KM = 32, ROWQ = 4;
-  static constexpr bool SPLIT = true;
+  static constexpr bool SPLIT = true, SCALED = false;
+};
+// FP16 parts of operands scaled by powers of two; the W build multiplies its
+// result by WItem::scale.
+template <> struct Tr<Prec::FP16X2> {
+  using T = uint16_t; using Acc = f4; using Out = float; using Frag = h8;
+  static constexpr int KT = 32, PAD = 0, NP = 2, KM = 32, ROWQ = 4;
+  static constexpr bool SPLIT = true, SCALED = true;
 };
 
 template <typename TR> struct Swz {
@@ -113,6 +121,9 @@ __device__ inline f4 mma(float a, float b, f4 c) {
 }
 __device__ inline f4 mma(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mma(h8 a, h8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
 __device__ inline long box_off(int a, int b, int c, int nT) {

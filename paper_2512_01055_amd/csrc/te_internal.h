@@ -16,7 +16,7 @@ constexpr int BOX3 = BOX * BOX * BOX;
 
 inline int pad_v(int v) { return (v + VPAD - 1) / VPAD * VPAD; }
 
-enum class Prec : int { F64 = 0, F32 = 1, BF16X3 = 2, BF16X2 = 3 };
+enum class Prec : int { F64 = 0, F32 = 1, BF16X3 = 2, BF16X2 = 3, FP16X2 = 4 };
 
 // One occupied triple's W build: three GEMMs (one per lone virtual index),
 // each M = vp^2 (virtual pairs) x N = vp (lone index) x K = 2 vp + 2 o.
@@ -39,6 +39,7 @@ struct WItem {
                    // FP64 and FP32 modes, o rounded up to 8 (zero padded) in
                    // BF16 modes
   void *W;         // three boxed W arrays of vp^3 each (FP64 or FP32)
+  float scale;     // FP16 parts: 1 / (sigma_X sigma_T), applied to W; else 1
   int o, vp, i, j, k;
   int mt, nt;      // tiles along M and N
 };
@@ -109,6 +110,19 @@ hipError_t launch_to_bf16_parts(const double *src, uint16_t *dst, size_t n, int 
 // occupied index from its FP64 column panel [o][v][v]; see panel_kernel.
 hipError_t launch_panel(Prec p, const double *stg, void *col, void *row, int o, int v, int vp,
                         int lo, hipStream_t s);
+// Scaled FP16 parts (two, [2][n]) of sigma * x, in the layouts of the BF16
+// launchers above; sigma is a power of two.
+hipError_t launch_to_f16_parts(const double *src, uint16_t *dst, size_t n, double sigma,
+                               hipStream_t s);
+hipError_t launch_t2t_f16_parts(const double *t2, uint16_t *dst, int o, int vp, int lo,
+                                double sigma, hipStream_t s);
+hipError_t launch_in_f16_parts(const double *in, uint16_t *dst, int o, int vp, int lo,
+                               double sigma, hipStream_t s);
+// Max |x| (absmax) or max over columns of sum_Q B[Q][c]^2 (colnorm_max), into
+// *out as the bits of a non-negative double; *out must start at 0.
+hipError_t launch_absmax(const double *x, size_t n, unsigned long long *out, hipStream_t s);
+hipError_t launch_colnorm_max(const double *B, int naux, long ncol, unsigned long long *out,
+                              hipStream_t s);
 hipError_t launch_t2t_bf16_parts(const double *t2, uint16_t *dst, int o, int vp, int lo,
                                  int nparts, hipStream_t s);
 // BF16 parts of In [o][vp][o][o] with the last index padded to lo.

@@ -33,7 +33,7 @@ te_status set_error(te_status s, const std::string &m);
   catch (...) { return ::te::set_error(TE_EDEVICE, "unexpected exception"); }
 
 inline Prec to_prec(te_precision p) {
-  if (p < TE_FP64 || p > TE_BF16X2) throw Fail(TE_EINVAL, "bad precision");
+  if (p < TE_FP64 || p > TE_FP16X2) throw Fail(TE_EINVAL, "bad precision");
   return static_cast<Prec>(p);
 }
 
@@ -75,6 +75,8 @@ struct Operands {
   const void *X = nullptr, *T2 = nullptr, *In = nullptr, *T2T = nullptr;
   size_t xps = 0, tps = 0, ips = 0, t2tps = 0;
   int lo = 0;     // occupied row length of In / T2T
+  float scale = 1.0f;  // FP16 parts: 1 / (sigma_X sigma_T); 1 otherwise
+  double sigma_x = 1.0, sigma_t = 1.0;
   DBuf X_own, T2_own, In_own, T2T_own;
 };
 
@@ -96,7 +98,10 @@ struct Job {
   const double *t2h = nullptr;     // host t2 [o][o][v][v] when it stays in host memory
   DBuf Bov_own, Boo_own, Bvv_own;
   const double *Bov = nullptr, *Boo = nullptr, *Bvv = nullptr;
-  Operands op[4];
+  // max |(px|yf)| bound from the factors, max_px |B_px| max_yf |B_yf| (set
+  // at staging, while the factors are present; 0 with explicit integrals)
+  double x_bound = 0.0;
+  Operands op[5];
   // On-the-fly mode: the (vv|vo) slice cache and which occupied index each
   // slot holds (-1: empty), kept across calls in one precision so that a job
   // evaluated in pieces does not start from a cold cache.

@@ -269,24 +269,31 @@ __device__ inline double bf16_val(uint16_t h) {
 }
 
 // x ~ sum_p h_p, h_p = bf16(x - sum_{q<p} h_q); parts stored [part][n]
-__global__ void to_bf16_parts_kernel(const double *__restrict__ src, uint16_t *__restrict__ dst,
-                                     size_t n, int nparts) {
-  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
-       q += (size_t)gridDim.x * blockDim.x) {
-    double r = src[q];
-    for (int p = 0; p < nparts; ++p) {
-      uint16_t h = bf16_rne((float)r);
-      dst[p * n + q] = h;
-      r -= bf16_val(h);
-    }
-  }
-}
-
 __device__ inline void split_store(double r, uint16_t *dst, size_t q, size_t n, int nparts) {
   for (int p = 0; p < nparts; ++p) {
     uint16_t h = bf16_rne((float)r);
     dst[p * n + q] = h;
     r -= bf16_val(h);
+  }
+}
+
+// y = sigma x ~ h_0 + h_1 with h_0 = f16(y), h_1 = f16(y - h_0) (round to
+// nearest even; sigma a power of two, so the scaling is exact); parts [2][n]
+__device__ inline void split_store_f16(double x, uint16_t *dst, size_t q, size_t n, double sigma) {
+  const double y = x * sigma;
+  const _Float16 h0 = (_Float16)y;
+  const _Float16 h1 = (_Float16)(y - (double)h0);
+  dst[q] = __builtin_bit_cast(uint16_t, h0);
+  dst[n + q] = __builtin_bit_cast(uint16_t, h1);
+}
+
+// parts stored [part][n]: BF16 (sigma == 0) or scaled FP16 (sigma != 0)
+__global__ void to_bf16_parts_kernel(const double *__restrict__ src, uint16_t *__restrict__ dst,
+                                     size_t n, int nparts, double sigma) {
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x) {
+    if (sigma != 0.0) split_store_f16(src[q], dst, q, n, sigma);
+    else split_store(src[q], dst, q, n, nparts);
   }
 }
 
@@ -337,7 +344,7 @@ __global__ void panel_kernel(const double *__restrict__ stg, OT *__restrict__ co
 }
 
 __global__ void t2t_bf16_kernel(const double *__restrict__ t2, uint16_t *__restrict__ dst, int o,
-                                int vp, int lo, int nparts) {
+                                int vp, int lo, int nparts, double sigma) {
   const long vp2 = (long)vp * vp;
   const size_t n = (size_t)o * vp2 * lo;
   for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
@@ -347,19 +354,21 @@ __global__ void t2t_bf16_kernel(const double *__restrict__ t2, uint16_t *__restr
     const long pair = (long)(r % vp2);
     const int p = (int)(r / vp2);
     const double x = l < o ? t2[((long)p * o + l) * vp2 + pair] : 0.0;
-    split_store(x, dst, q, n, nparts);
+    if (sigma != 0.0) split_store_f16(x, dst, q, n, sigma);
+    else split_store(x, dst, q, n, nparts);
   }
 }
 
 __global__ void in_bf16_kernel(const double *__restrict__ in, uint16_t *__restrict__ dst, int o,
-                               int vp, int lo, int nparts) {
+                               int vp, int lo, int nparts, double sigma) {
   const size_t n = (size_t)o * vp * o * lo;
   for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
        q += (size_t)gridDim.x * blockDim.x) {
     const int l = (int)(q % lo);
     const size_t r = q / lo;                  // (p, x, q') row
     const double x = l < o ? in[r * o + l] : 0.0;
-    split_store(x, dst, q, n, nparts);
+    if (sigma != 0.0) split_store_f16(x, dst, q, n, sigma);
+    else split_store(x, dst, q, n, nparts);
   }
 }
 
@@ -391,6 +400,50 @@ __global__ void t2_asym_kernel(const double *__restrict__ t2, int o, int v,
   }
   atomicMax(&out[0], (unsigned long long)__double_as_longlong(md));
   atomicMax(&out[1], (unsigned long long)__double_as_longlong(ma));
+}
+
+// max |x| over n doubles into *out (as the bit pattern of a non-negative
+// double, which orders like an unsigned integer; *out starts at 0)
+__global__ void absmax_kernel(const double *__restrict__ x, size_t n,
+                              unsigned long long *out) {
+  __shared__ double red[WG / 64];
+  double m = 0.0;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(x[q]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < WG / 64; ++w) m = fmax(m, red[w]);
+    atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// max over columns c of sum_Q B[Q][c]^2, B stored [naux][ncol], into *out as
+// absmax_kernel does
+__global__ void colnorm_max_kernel(const double *__restrict__ B, int naux, long ncol,
+                                   unsigned long long *out) {
+  __shared__ double red[WG / 64];
+  double m = 0.0;
+  for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < ncol;
+       c += (long)gridDim.x * blockDim.x) {
+    double s2 = 0.0;
+    for (int Q = 0; Q < naux; ++Q) {
+      const double b = B[(long)Q * ncol + c];
+      s2 += b * b;
+    }
+    m = fmax(m, s2);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < WG / 64; ++w) m = fmax(m, red[w]);
+    atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 // ------------------------------------------------------------ MFMA rate probe
@@ -504,7 +557,7 @@ hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t s)
 
 hipError_t launch_to_bf16_parts(const double *src, uint16_t *dst, size_t n, int nparts,
                                 hipStream_t s) {
-  to_bf16_parts_kernel<<<blocks_for(n), WG, 0, s>>>(src, dst, n, nparts);
+  to_bf16_parts_kernel<<<blocks_for(n), WG, 0, s>>>(src, dst, n, nparts, 0.0);
   return hipGetLastError();
 }
 
@@ -525,17 +578,48 @@ hipError_t launch_panel(Prec p, const double *stg, void *col, void *row, int o, 
   return hipGetLastError();
 }
 
+hipError_t launch_to_f16_parts(const double *src, uint16_t *dst, size_t n, double sigma,
+                               hipStream_t s) {
+  to_bf16_parts_kernel<<<blocks_for(n), WG, 0, s>>>(src, dst, n, 2, sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_t2t_f16_parts(const double *t2, uint16_t *dst, int o, int vp, int lo,
+                                double sigma, hipStream_t s) {
+  size_t n = (size_t)o * vp * vp * lo;
+  t2t_bf16_kernel<<<blocks_for(n), WG, 0, s>>>(t2, dst, o, vp, lo, 2, sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_in_f16_parts(const double *in, uint16_t *dst, int o, int vp, int lo,
+                               double sigma, hipStream_t s) {
+  size_t n = (size_t)o * vp * o * lo;
+  in_bf16_kernel<<<blocks_for(n), WG, 0, s>>>(in, dst, o, vp, lo, 2, sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const double *x, size_t n, unsigned long long *out, hipStream_t s) {
+  absmax_kernel<<<blocks_for(n), WG, 0, s>>>(x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_colnorm_max(const double *B, int naux, long ncol, unsigned long long *out,
+                              hipStream_t s) {
+  colnorm_max_kernel<<<blocks_for((size_t)ncol), WG, 0, s>>>(B, naux, ncol, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_t2t_bf16_parts(const double *t2, uint16_t *dst, int o, int vp, int lo,
                                  int nparts, hipStream_t s) {
   size_t n = (size_t)o * vp * vp * lo;
-  t2t_bf16_kernel<<<blocks_for(n), WG, 0, s>>>(t2, dst, o, vp, lo, nparts);
+  t2t_bf16_kernel<<<blocks_for(n), WG, 0, s>>>(t2, dst, o, vp, lo, nparts, 0.0);
   return hipGetLastError();
 }
 
 hipError_t launch_in_bf16_parts(const double *in, uint16_t *dst, int o, int vp, int lo,
                                 int nparts, hipStream_t s) {
   size_t n = (size_t)o * vp * o * lo;
-  in_bf16_kernel<<<blocks_for(n), WG, 0, s>>>(in, dst, o, vp, lo, nparts);
+  in_bf16_kernel<<<blocks_for(n), WG, 0, s>>>(in, dst, o, vp, lo, nparts, 0.0);
   return hipGetLastError();
 }
 

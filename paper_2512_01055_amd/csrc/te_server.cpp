@@ -319,7 +319,7 @@ ServerImpl::Launch ServerImpl::launch_round() {
     w.Xs[1] = (const char *)op.X + (size_t)jj * vp3 * es;
     w.Xs[2] = (const char *)op.X + (size_t)k * vp3 * es;
     w.In = op.In;
-    w.xps = op.xps; w.ips = op.ips; w.lo = op.lo;
+    w.xps = op.xps; w.ips = op.ips; w.lo = op.lo; w.scale = op.scale;
     w.W = W; w.o = J.o; w.vp = (int)vp; w.i = i; w.j = jj; w.k = k;
     resident_t2_views(J, op, P, w);
     w.mt = (int)((vp * vp + bm - 1) / bm);
@@ -557,7 +557,7 @@ te_status te_submit(te_server srv, const te_problem *prob, te_precision prec, ui
   ServerImpl &S = *reinterpret_cast<ServerImpl *>(srv);
   if (!prob) return set_error(TE_EINVAL, "problem is NULL");
   if (prob->mem != TE_MEM_HOST) return set_error(TE_EINVAL, "te_submit takes host arrays");
-  if (prec < TE_FP64 || prec > TE_BF16X2) return set_error(TE_EINVAL, "bad precision");
+  if (prec < TE_FP64 || prec > TE_FP16X2) return set_error(TE_EINVAL, "bad precision");
   if (prob->o < 1 || prob->v < 1 || prob->naux < 0)
     return set_error(TE_EINVAL, "need o >= 1, v >= 1, naux >= 0");
   if (!prob->eps_occ || !prob->eps_vir || !prob->t1 || !prob->t2)

@@ -339,18 +339,19 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
 #pragma unroll
           for (int cb = 0; cb < NB; ++cb) acc[rb_][cb] = mma(av[rb_], bv[cb], acc[rb_][cb]);
       } else {
-        bf8 av[WM][NP], bv[NB][NP];
+        using F = typename TR::Frag;
+        F av[WM][NP], bv[NB][NP];
 #pragma unroll
         for (int rb_ = 0; rb_ < WM; ++rb_)
 #pragma unroll
           for (int p = 0; p < NP; ++p)
-            av[rb_][p] = *reinterpret_cast<const bf8 *>(
+            av[rb_][p] = *reinterpret_cast<const F *>(
                 &As[cur][p][wrow + rb_ * 16 + fr][lcol<TR>(wrow + rb_ * 16 + fr, fk * 8)]);
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
           for (int p = 0; p < NP; ++p)
-            bv[cb][p] = *reinterpret_cast<const bf8 *>(&Bs[cur][p][cb * 16 + fr][lcol<TR>(cb * 16 + fr, fk * 8)]);
+            bv[cb][p] = *reinterpret_cast<const F *>(&Bs[cur][p][cb * 16 + fr][lcol<TR>(cb * 16 + fr, fk * 8)]);
 #pragma unroll
         for (int rb_ = 0; rb_ < WM; ++rb_)
 #pragma unroll
@@ -385,7 +386,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
           if (g == 0) { a = p0; b = p1; c = n; }
           else if (g == 1) { a = n; b = p0; c = p1; }
           else { a = p0; b = n; c = p1; }
-          gst(Wg + box_off(a, b, c, nT), (Out)acc[rb_][cb][r]);
+          Out x = (Out)acc[rb_][cb][r];
+          if constexpr (TR::SCALED) x *= w.scale;
+          gst(Wg + box_off(a, b, c, nT), x);
         }
       }
 }
@@ -446,6 +449,7 @@ hipError_t launch_wbuild(Prec p, const WItem *d_items, const int *d_tile_item, i
     case Prec::F32: return launch_wb_p<Prec::F32>(d_items, d_tile_item, tiles_per_item, total_tiles, c, s);
     case Prec::BF16X3: return launch_wb_p<Prec::BF16X3>(d_items, d_tile_item, tiles_per_item, total_tiles, c, s);
     case Prec::BF16X2: return launch_wb_p<Prec::BF16X2>(d_items, d_tile_item, tiles_per_item, total_tiles, c, s);
+    case Prec::FP16X2: return launch_wb_p<Prec::FP16X2>(d_items, d_tile_item, tiles_per_item, total_tiles, c, s);
   }
   return hipErrorInvalidValue;
 }

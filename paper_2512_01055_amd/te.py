@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libte.so")
 
 OK, PENDING, EINVAL, ENOMEM, EDEVICE, EBUSY, ENOTFOUND, ECANCELED, EIO = 0, 1, -1, -2, -3, -4, -5, -6, -7
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3, "fp16x2": 4}
 X_MODES = {"auto": 0, "resident": 1, "on_the_fly": 2}
 
 

@@ -22,8 +22,8 @@ from paper_2512_01055_amd.inputs import LARGE, MEDIUM, make_problem, sample_trip
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-TOL = {"fp64": 1e-8, "fp32": 1e-6, "bf16x3": 1e-6, "bf16x2": 1e-6}
-PRECS = ["fp64", "fp32", "bf16x3", "bf16x2"]
+TOL = {"fp64": 1e-8, "fp32": 1e-6, "bf16x3": 1e-6, "bf16x2": 1e-6, "fp16x2": 1e-6}
+PRECS = ["fp64", "fp32", "bf16x3", "bf16x2", "fp16x2"]
 
 
 def _te():
@@ -212,7 +212,7 @@ def test_budget_too_small_is_enomem():
     assert ei.value.status == te.ENOMEM
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "fp16x2"])
 @pytest.mark.parametrize("slices", [3, 4, 7])
 def test_on_the_fly_slices_equal_resident(prec, slices):
     """(vv|vo) assembled from the factors into a small slice cache (many
@@ -273,10 +273,13 @@ def test_precision_switch_rebuilds_reduced_copies():
         E32a, _, pa = job.energy("fp32", per_triple=True)
         E16, _, _ = job.energy("bf16x2", per_triple=True)
         E16b, _, _ = job.energy("bf16x3", per_triple=True)
+        Eh, _, ph = job.energy("fp16x2", per_triple=True)
         E32b, _, pb = job.energy("fp32", per_triple=True)
+        Eh2, _, ph2 = job.energy("fp16x2", per_triple=True)
         E64, _ = job.energy("fp64")
     assert E32a == E32b and np.array_equal(pa, pb)
-    for E in (E32a, E16, E16b):
+    assert Eh == Eh2 and np.array_equal(ph, ph2)
+    for E in (E32a, E16, E16b, Eh):
         assert abs(E - E64) <= 1e-6 * abs(E64)
 
 
@@ -375,14 +378,18 @@ def test_host_t2_panels_equal_resident(shape):
     te = _te()
     P = make_problem(o, v, naux, seed)
     ref = {}
+    host_precs = [p_ for p_ in PRECS if p_ != "fp16x2"]    # FP16 parts need t2 on the device
     with te.Job(P, device=0, x_mode="resident") as job:
-        for prec in PRECS:
+        for prec in host_precs:
             ref[prec] = job.energy(prec, per_triple=True)[2]
     sub = sample_triples(o, 8, 3)
     allt = te.triple_list(o)
     idx = [int(np.nonzero((allt == s_).all(1))[0][0]) for s_ in sub]
     with te.Job(P, device=0, t2_host=True, x_cache_slices=slices, validate=True) as job:
-        for prec in PRECS:
+        with pytest.raises(te.TeError) as ei:
+            job.energy("fp16x2")
+        assert ei.value.status == te.EINVAL
+        for prec in host_precs:
             print(f"\n[host t2 o={o} v={v} prec={prec}]", flush=True)
             E, st, pt = job.energy(prec, per_triple=True)
             assert np.array_equal(pt, ref[prec]), prec

@@ -42,8 +42,8 @@ def test_mix_equals_alone_bitwise(prec):
 
 def test_mixed_precisions_in_one_server():
     te = _te()
-    probs = [make_problem(*m) for m in MIX[:4]]
-    precs = ["fp64", "bf16x2", "fp32", "bf16x3"]
+    probs = [make_problem(*m) for m in MIX[:5]]
+    precs = ["fp64", "bf16x2", "fp32", "bf16x3", "fp16x2"]
     alone = [_alone(te, P, p) for P, p in zip(probs, precs)]
     with te.Server(device=0) as srv:
         tickets = [srv.submit(P, p) for P, p in zip(probs, precs)]
