@@ -16,6 +16,8 @@
  * All functions are extern "C", never throw, and report through te_status.
  * A failing call leaves its output arguments untouched; te_last_error()
  * returns a message for the calling thread's most recent failure.
+ * Different jobs may be used from different threads at once; calls on one
+ * job must not overlap (they share its streams and slice cache).
  */
 #ifndef TE_H
 #define TE_H
@@ -51,7 +53,7 @@ typedef enum te_precision {
   TE_BF16X2 = 3,  /* 2 BF16 parts, 3 cross products, FP32 accumulation         */
   TE_FP16X2 = 4   /* operands scaled by a power of two per operand family and
                      split into 2 FP16 parts, 3 cross products, FP32
-                     accumulation, unscaled at the end (not with t2_host)      */
+                     accumulation, unscaled at the end                          */
 } te_precision;
 
 typedef enum te_memkind { TE_MEM_HOST = 0, TE_MEM_DEVICE = 1 } te_memkind;
@@ -251,11 +253,12 @@ te_status te_wait(te_server srv, uint64_t ticket, double *e_t, te_stats *st);
 te_status te_server_destroy(te_server srv);
 
 /* Diagnostic: the sustained matrix-core rate of `device` for the MFMA form
- * the W build uses in `prec` (FP64, FP32 or BF16 16x16 blocks), measured
+ * the W build uses in `prec` (FP64, FP32, BF16 or FP16 16x16 blocks), measured
  * with a register-only kernel that keeps every SIMD issuing independent
  * MFMA chains for about `seconds`. Puts a kernel's fraction of the published
  * peak in context (clocks under sustained matrix load sit below the peak
- * clock). Writes TFLOP/s of the instruction itself (for BF16: per product). */
+ * clock). Writes TFLOP/s of the instruction itself (for the split modes: per
+ * product; BF16X3 and BF16X2 time the BF16 instruction, FP16X2 the FP16 one). */
 te_status te_mfma_sustained(int device, te_precision prec, double seconds, double *tflops);
 
 const char *te_strerror(te_status s);

@@ -210,6 +210,22 @@ static double dev_colnorm_max(Job &J, const double *B, long ncol) {
   HIPCHK(launch_colnorm_max(B, J.naux, ncol, m.as<unsigned long long>(), J.s_main));
   return read_max(J, m);
 }
+// Largest |x| over n host doubles, on a few threads.
+static double host_absmax(const double *x, size_t n) {
+  const size_t nth = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  std::vector<double> part(nth, 0.0);
+  auto run = [&](size_t t) {
+    double m = 0.0;
+    for (size_t q = t * n / nth, e = (t + 1) * n / nth; q < e; ++q) m = std::max(m, std::abs(x[q]));
+    part[t] = m;
+  };
+  std::vector<std::thread> th;
+  for (size_t t = 1; t < nth; ++t) th.emplace_back(run, t);
+  run(0);
+  for (auto &x_ : th) x_.join();
+  return *std::max_element(part.begin(), part.end());
+}
+
 // 2^k with k the largest integer such that 2^k m <= 2^14 (1 for m = 0)
 static double pow2_scale(double m) {
   if (!(m > 0.0) || !std::isfinite(m)) return 1.0;
@@ -384,7 +400,6 @@ const Operands &ensure_prec(Job &J, Prec p) {
     // two FP16 parts of sigma x; sigma_x scales X and In (their products with
     // t2 share one accumulator), sigma_t scales t2, each bringing the largest
     // magnitude to at most 2^14 (FP16 holds up to 65504)
-    if (!J.t2) throw Fail(TE_EINVAL, "FP16 parts need t2 in device memory");
     const int lo = (o + 7) / 8 * 8;
     const size_t nInP = (size_t)o * vp * o * lo, nT2T = (size_t)o * vp * vp * lo;
     double mx = dev_absmax(J, J.In.as<double>(), nIn);
@@ -396,16 +411,20 @@ const Operands &ensure_prec(Job &J, Prec p) {
       mx = std::max(mx, dev_absmax(J, J.X.as<double>(), nX));
     }
     op.sigma_x = pow2_scale(mx);
-    op.sigma_t = pow2_scale(dev_absmax(J, J.t2, nT2));
+    // (host t2: the same maximum, taken on the host; its panels are scaled
+    // as they enter the slice cache)
+    op.sigma_t = pow2_scale(J.t2 ? dev_absmax(J, J.t2, nT2) : host_absmax(J.t2h, (size_t)o * o * J.v * J.v));
     op.scale = (float)(1.0 / (op.sigma_x * op.sigma_t));
-    jalloc(J, op.T2_own, nT2 * 2 * 2);
     jalloc(J, op.In_own, nInP * 2 * 2);
-    jalloc(J, op.T2T_own, nT2T * 2 * 2);
-    HIPCHK(launch_to_f16_parts(J.t2, op.T2_own.as<uint16_t>(), nT2, op.sigma_t, J.s_main));
     HIPCHK(launch_in_f16_parts(J.In.as<double>(), op.In_own.as<uint16_t>(), o, vp, lo,
                                op.sigma_x, J.s_main));
-    HIPCHK(launch_t2t_f16_parts(J.t2, op.T2T_own.as<uint16_t>(), o, vp, lo, op.sigma_t,
-                                J.s_main));
+    if (J.t2) {
+      jalloc(J, op.T2_own, nT2 * 2 * 2);
+      jalloc(J, op.T2T_own, nT2T * 2 * 2);
+      HIPCHK(launch_to_f16_parts(J.t2, op.T2_own.as<uint16_t>(), nT2, op.sigma_t, J.s_main));
+      HIPCHK(launch_t2t_f16_parts(J.t2, op.T2T_own.as<uint16_t>(), o, vp, lo, op.sigma_t,
+                                  J.s_main));
+    }
     if (nX) {
       jalloc(J, op.X_own, nX * 2 * 2);
       HIPCHK(launch_to_f16_parts(J.X.as<double>(), op.X_own.as<uint16_t>(), nX, op.sigma_x,
@@ -606,8 +625,9 @@ static void fill_panels(Job &J, Prec p, int occ, char *col, char *row, hipStream
   for (auto &x : th) x.join();
   HIPCHK(hipMemcpyAsync(J.xc.tstg.p, J.xc.pinned, o * v2 * 8, hipMemcpyHostToDevice, s));
   HIPCHK(hipEventRecord(J.xc.pinned_free, s));
-  const int lo = nparts(p) == 3 ? (J.o + 7) / 8 * 8 : J.o;
-  HIPCHK(launch_panel(p, J.xc.tstg.as<double>(), col, row, J.o, J.v, J.vp, lo, s));
+  const int lo = p == Prec::F64 || p == Prec::F32 ? J.o : (J.o + 7) / 8 * 8;
+  HIPCHK(launch_panel(p, J.xc.tstg.as<double>(), col, row, J.o, J.v, J.vp, lo,
+                      J.op[(int)Prec::FP16X2].sigma_t, s));
 }
 
 std::vector<int> checked_triples(const Job &J, const int32_t *ijk, int64_t n) {
@@ -709,8 +729,9 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
   const size_t vp2 = (size_t)vp * vp;
   const size_t x_bytes = vp3 * es * (size_t)nparts(p);
   const size_t col_bytes = J.t2h ? (size_t)o * vp2 * es * nparts(p) : 0;
+  const bool row_form = p != Prec::F64 && p != Prec::F32;   // 16-bit parts, l last
   const size_t row_bytes =
-      J.t2h ? (nparts(p) == 3 ? vp2 * (size_t)op.lo * es * 3 : (size_t)o * vp2 * es) : 0;
+      J.t2h ? (row_form ? vp2 * (size_t)op.lo * es * nparts(p) : (size_t)o * vp2 * es) : 0;
   std::vector<int> after;   // slot contents once this call completes
   if (fly) {
     slot_bytes = x_bytes + col_bytes + row_bytes;

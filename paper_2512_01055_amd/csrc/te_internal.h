@@ -106,10 +106,11 @@ hipError_t launch_to_bf16_parts(const double *src, uint16_t *dst, size_t n, int 
                                 hipStream_t s);
 // BF16 parts of t2 [o][o][vp][vp] regrouped as [part][o][vp*vp][lo] (occupied
 // index last, zero for l >= o).
-// Column panel and row panel (FP64, FP32) or row form (BF16 parts) of one
+// Column panel and row panel (FP64, FP32) or row form (16-bit parts) of one
 // occupied index from its FP64 column panel [o][v][v]; see panel_kernel.
+// sigma: the t2 scale of the FP16 parts (ignored otherwise).
 hipError_t launch_panel(Prec p, const double *stg, void *col, void *row, int o, int v, int vp,
-                        int lo, hipStream_t s);
+                        int lo, double sigma, hipStream_t s);
 // Scaled FP16 parts (two, [2][n]) of sigma * x, in the layouts of the BF16
 // launchers above; sigma is a power of two.
 hipError_t launch_to_f16_parts(const double *src, uint16_t *dst, size_t n, double sigma,

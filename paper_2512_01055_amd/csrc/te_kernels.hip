@@ -306,13 +306,22 @@ __global__ void to_bf16_parts_kernel(const double *__restrict__ src, uint16_t *_
 //   row[part][y vp + z][l]  = t2[p][l][y][z] = stg[l][z][y], l < lo (BF16 parts)
 __device__ inline void put(double *d, size_t q, size_t, double x, int) { d[q] = x; }
 __device__ inline void put(float *d, size_t q, size_t, double x, int) { d[q] = (float)x; }
-__device__ inline void put(uint16_t *d, size_t q, size_t n, double x, int np) {
-  split_store(x, d, q, n, np);
+__device__ inline void put(uint16_t *d, size_t q, size_t n, double x, int np, double sigma) {
+  if (sigma != 0.0) split_store_f16(x, d, q, n, sigma);
+  else split_store(x, d, q, n, np);
+}
+__device__ inline void put(double *d, size_t q, size_t n, double x, int np, double) {
+  put(d, q, n, x, np);
+}
+__device__ inline void put(float *d, size_t q, size_t n, double x, int np, double) {
+  put(d, q, n, x, np);
 }
 
+// (16-bit parts: BF16 with sigma == 0, scaled FP16 otherwise)
 template <typename OT>
 __global__ void panel_kernel(const double *__restrict__ stg, OT *__restrict__ col,
-                             OT *__restrict__ row, int o, int v, int vp, int lo, int nparts) {
+                             OT *__restrict__ row, int o, int v, int vp, int lo, int nparts,
+                             double sigma) {
   constexpr bool form = sizeof(OT) == 2;
   const long vp2 = (long)vp * vp;
   const size_t ncol = (size_t)o * vp2;
@@ -324,21 +333,21 @@ __global__ void panel_kernel(const double *__restrict__ stg, OT *__restrict__ co
       const size_t r = q / vp;
       const int a = (int)(r % vp), l = (int)(r / vp);
       const double x = (a < v && b < v) ? stg[((size_t)l * v + a) * v + b] : 0.0;
-      put(col, q, ncol, x, nparts);
+      put(col, q, ncol, x, nparts, sigma);
     } else if (form) {
       const size_t qq = q - ncol;
       const int l = (int)(qq % lo);
       const long pair = (long)(qq / lo);
       const int y = (int)(pair / vp), z = (int)(pair % vp);
       const double x = (l < o && y < v && z < v) ? stg[((size_t)l * v + z) * v + y] : 0.0;
-      put(row, qq, nrow, x, nparts);
+      put(row, qq, nrow, x, nparts, sigma);
     } else {
       const size_t qq = q - ncol;
       const int b = (int)(qq % vp);
       const size_t r = qq / vp;
       const int a = (int)(r % vp), l = (int)(r / vp);
       const double x = (a < v && b < v) ? stg[((size_t)l * v + b) * v + a] : 0.0;
-      put(row, qq, nrow, x, nparts);
+      put(row, qq, nrow, x, nparts, sigma);
     }
   }
 }
@@ -491,6 +500,20 @@ __global__ __launch_bounds__(WG) void probe_bf16(float *out, int iters) {
   gst(out + blockIdx.x * (long)WG + threadIdx.x, s);
 }
 
+__global__ __launch_bounds__(WG) void probe_f16(float *out, int iters) {
+  f4 acc[8];
+  for (int c = 0; c < 8; ++c) acc[c] = f4{0, 0, 0, 0};
+  h8 x, y;
+  for (int e = 0; e < 8; ++e) {
+    x[e] = (_Float16)(float)((threadIdx.x + e) & 7);
+    y[e] = (_Float16)(float)(e - 3);
+  }
+  mfma_chains<h8, f4, 8>(x, y, acc, iters);
+  float s = 0;
+  for (int c = 0; c < 8; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  gst(out + blockIdx.x * (long)WG + threadIdx.x, s);
+}
+
 }  // namespace
 
 // flops of one probe launch: blocks x 4 waves x 8 chains x iters x MFMA flops
@@ -501,6 +524,7 @@ hipError_t launch_mfma_probe(Prec p, void *out, int blocks, int iters, hipStream
   *flops = per * 8.0 * iters * blocks * (WG / 64);
   if (p == Prec::F64) probe_f64<<<blocks, WG, 0, s>>>((double *)out, iters);
   else if (p == Prec::F32) probe_f32<<<blocks, WG, 0, s>>>((float *)out, iters);
+  else if (p == Prec::FP16X2) probe_f16<<<blocks, WG, 0, s>>>((float *)out, iters);
   else probe_bf16<<<blocks, WG, 0, s>>>((float *)out, iters);
   return hipGetLastError();
 }
@@ -562,19 +586,22 @@ hipError_t launch_to_bf16_parts(const double *src, uint16_t *dst, size_t n, int 
 }
 
 hipError_t launch_panel(Prec p, const double *stg, void *col, void *row, int o, int v, int vp,
-                        int lo, hipStream_t s) {
+                        int lo, double sigma, hipStream_t s) {
   const size_t ncol = (size_t)o * vp * vp;
-  const bool split = p == Prec::BF16X3 || p == Prec::BF16X2;
+  const bool split = p == Prec::BF16X3 || p == Prec::BF16X2 || p == Prec::FP16X2;
   const size_t n = ncol + (split ? (size_t)vp * vp * lo : ncol);
   if (p == Prec::F64)
     panel_kernel<double><<<blocks_for(n), WG, 0, s>>>(stg, (double *)col, (double *)row, o, v,
-                                                      vp, lo, 1);
+                                                      vp, lo, 1, 0.0);
   else if (p == Prec::F32)
     panel_kernel<float><<<blocks_for(n), WG, 0, s>>>(stg, (float *)col, (float *)row, o, v, vp,
-                                                     lo, 1);
+                                                     lo, 1, 0.0);
+  else if (p == Prec::FP16X2)
+    panel_kernel<uint16_t><<<blocks_for(n), WG, 0, s>>>(stg, (uint16_t *)col, (uint16_t *)row,
+                                                        o, v, vp, lo, 2, sigma);
   else
     panel_kernel<uint16_t><<<blocks_for(n), WG, 0, s>>>(stg, (uint16_t *)col, (uint16_t *)row,
-                                                        o, v, vp, lo, 3);
+                                                        o, v, vp, lo, 3, 0.0);
   return hipGetLastError();
 }
 

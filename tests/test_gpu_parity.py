@@ -378,18 +378,14 @@ def test_host_t2_panels_equal_resident(shape):
     te = _te()
     P = make_problem(o, v, naux, seed)
     ref = {}
-    host_precs = [p_ for p_ in PRECS if p_ != "fp16x2"]    # FP16 parts need t2 on the device
     with te.Job(P, device=0, x_mode="resident") as job:
-        for prec in host_precs:
+        for prec in PRECS:
             ref[prec] = job.energy(prec, per_triple=True)[2]
     sub = sample_triples(o, 8, 3)
     allt = te.triple_list(o)
     idx = [int(np.nonzero((allt == s_).all(1))[0][0]) for s_ in sub]
     with te.Job(P, device=0, t2_host=True, x_cache_slices=slices, validate=True) as job:
-        with pytest.raises(te.TeError) as ei:
-            job.energy("fp16x2")
-        assert ei.value.status == te.EINVAL
-        for prec in host_precs:
+        for prec in PRECS:
             print(f"\n[host t2 o={o} v={v} prec={prec}]", flush=True)
             E, st, pt = job.energy(prec, per_triple=True)
             assert np.array_equal(pt, ref[prec]), prec
