@@ -275,7 +275,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by "
-              "occupied triples across GPUs, which this build does not launch", file=sys.stderr)
+              "occupied triples across GPUs, which is not launched here", file=sys.stderr)
         return 2
     if args.workload == "huge":
         return bench_huge(args)
