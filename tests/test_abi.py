@@ -69,6 +69,10 @@ def test_argument_errors_need_no_device():
     assert lib.te_init(C.byref(p), None, C.byref(h)) == te.EINVAL   # explicit ints missing
     p.naux = -1
     assert lib.te_init(C.byref(p), None, C.byref(h)) == te.EINVAL
+    p.naux, p.v = 3, 8185                 # vp / 8 box indices must fit 10 bits
+    assert lib.te_init(C.byref(p), None, C.byref(h)) == te.EINVAL
+    assert b"v above" in lib.te_last_error()
+    p.v = 4
     # t2 in host memory: needs the factors, host arrays, and no resident slices
     p.naux = 3
     p.B_vv = x.ctypes.data

@@ -392,3 +392,23 @@ def test_host_t2_panels_equal_resident(shape):
             assert st["slices_assembled"] > o
             _, ps, _ = job.energy_triples(sub, prec)
             assert np.array_equal(ps, ref[prec][idx])
+
+
+def test_degenerate_sizes_and_empty_lists():
+    """o = 1 has no triples (E = 0); with v = 1 every Z vanishes (a = b = c), so
+    E is zero up to rounding, as in the oracle; an empty triple list gives 0."""
+    te = _te()
+    P = make_problem(1, 16, 12, 51)
+    with te.Job(P, device=0) as job:
+        for prec in PRECS:
+            E, st = job.energy(prec)
+            assert E == 0.0 and st["n_triples"] == 0
+    P = make_problem(4, 1, 6, 52)
+    E_ref, _, _ = oracle_parts("v1", P)
+    with te.Job(P, device=0) as job:
+        for prec in PRECS:
+            E, st, pt = job.energy(prec, per_triple=True)
+            assert st["n_triples"] == 16
+            assert abs(E) <= 1e-12 and abs(E_ref) <= 1e-12
+            Es, ps, st = job.energy_triples(np.zeros((0, 3), dtype=np.int32), prec)
+            assert Es == 0.0 and len(ps) == 0 and st["n_triples"] == 0
