@@ -245,7 +245,7 @@ void stage_df_slices(Job &J, const int *occ, int n, double *dst, size_t slice_st
   const long vp2 = (long)vp * vp;
   for (int q = 0; q < n; ++q) {
     double *C = dst + (size_t)q * slice_stride;
-    HIPCHK(hipMemsetAsync(C, 0, (size_t)vp2 * vp * sizeof(double), J.s_main));
+    if (v != vp) HIPCHK(hipMemsetAsync(C, 0, (size_t)vp2 * vp * sizeof(double), J.s_main));
     gemm_stage(J, J.Bov + (long)occ[q] * v, (long)o * v, J.Bvv, (long)v * v, v, v * v, naux,
                v, vp2, vp2, v, vp, 1, 1.0, C);
   }
@@ -595,7 +595,8 @@ static void assemble_slice(Job &J, Prec p, int occ, void *slot, double *tmp64, h
   const long vp2 = (long)vp * vp;
   const size_t n = (size_t)vp2 * vp;
   double *dst = p == Prec::F64 ? (double *)slot : tmp64;
-  HIPCHK(hipMemsetAsync(dst, 0, n * sizeof(double), s));
+  // the product writes every element unless v is padded; padding must read 0
+  if (v != vp) HIPCHK(hipMemsetAsync(dst, 0, n * sizeof(double), s));
   GemmTN g{J.Bov + (long)occ * v, J.Bvv, dst, v, v * v, naux, (long)o * v, (long)v * v,
            v, vp2, vp2, v, vp, 1, 1.0};
   HIPCHK(launch_gemm_tn(g, s));
