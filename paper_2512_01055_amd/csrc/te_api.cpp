@@ -155,7 +155,7 @@ static size_t elem_size(Prec p) {
   return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2);
 }
 static int nparts(Prec p) {
-  return p == Prec::BF16X3 || p == Prec::BF16X2 ? 3 : (p == Prec::FP16X2 ? 2 : 1);
+  return p == Prec::BF16X3 ? 3 : (p == Prec::BF16X2 || p == Prec::FP16X2 ? 2 : 1);
 }
 static size_t out_size(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
@@ -360,7 +360,7 @@ static void drop_operands(Operands &op) {
 }
 
 const Operands &ensure_prec(Job &J, Prec p) {
-  int slot = (p == Prec::BF16X2) ? (int)Prec::BF16X3 : (int)p;
+  const int slot = (int)p;
   Operands &op = J.op[slot];
   if (op.ready) return op;
   // at most one reduced-precision copy at a time: it is rebuilt from the
@@ -368,7 +368,7 @@ const Operands &ensure_prec(Job &J, Prec p) {
   if (p != Prec::F64) {
     HIPCHK(hipStreamSynchronize(J.s_main));
     if (J.s_aux) HIPCHK(hipStreamSynchronize(J.s_aux));
-    for (int q : {(int)Prec::F32, (int)Prec::BF16X3, (int)Prec::FP16X2})
+    for (int q : {(int)Prec::F32, (int)Prec::BF16X3, (int)Prec::BF16X2, (int)Prec::FP16X2})
       if (q != slot) drop_operands(J.op[q]);
   }
   const int o = J.o, vp = J.vp;
@@ -433,22 +433,24 @@ const Operands &ensure_prec(Job &J, Prec p) {
     op.X = op.X_own.p; op.T2 = op.T2_own.p; op.In = op.In_own.p; op.T2T = op.T2T_own.p;
     op.xps = nX; op.tps = nT2; op.ips = nInP; op.t2tps = nT2T; op.lo = lo;
   } else {
-    // BF16 parts; the occupied-index operands get l last and padded to 8 so
-    // the W build loads them as 16-byte chunks
+    // BF16 parts (three, or the first two of the same split); the
+    // occupied-index operands get l last and padded to 8 so the W build loads
+    // them as 16-byte chunks
+    const int np = nparts(p);
     const int lo = (o + 7) / 8 * 8;
     const size_t nInP = (size_t)o * vp * o * lo, nT2T = (size_t)o * vp * vp * lo;
-    jalloc(J, op.In_own, nInP * 2 * 3);
-    HIPCHK(launch_in_bf16_parts(J.In.as<double>(), op.In_own.as<uint16_t>(), o, vp, lo, 3,
+    jalloc(J, op.In_own, nInP * 2 * np);
+    HIPCHK(launch_in_bf16_parts(J.In.as<double>(), op.In_own.as<uint16_t>(), o, vp, lo, np,
                                 J.s_main));
     if (J.t2) {
-      jalloc(J, op.T2_own, nT2 * 2 * 3);
-      jalloc(J, op.T2T_own, nT2T * 2 * 3);
-      HIPCHK(launch_to_bf16_parts(J.t2, op.T2_own.as<uint16_t>(), nT2, 3, J.s_main));
-      HIPCHK(launch_t2t_bf16_parts(J.t2, op.T2T_own.as<uint16_t>(), o, vp, lo, 3, J.s_main));
+      jalloc(J, op.T2_own, nT2 * 2 * np);
+      jalloc(J, op.T2T_own, nT2T * 2 * np);
+      HIPCHK(launch_to_bf16_parts(J.t2, op.T2_own.as<uint16_t>(), nT2, np, J.s_main));
+      HIPCHK(launch_t2t_bf16_parts(J.t2, op.T2T_own.as<uint16_t>(), o, vp, lo, np, J.s_main));
     }
     if (nX) {
-      jalloc(J, op.X_own, nX * 2 * 3);
-      HIPCHK(launch_to_bf16_parts(J.X.as<double>(), op.X_own.as<uint16_t>(), nX, 3, J.s_main));
+      jalloc(J, op.X_own, nX * 2 * np);
+      HIPCHK(launch_to_bf16_parts(J.X.as<double>(), op.X_own.as<uint16_t>(), nX, np, J.s_main));
     }
     op.X = op.X_own.p; op.T2 = op.T2_own.p; op.In = op.In_own.p; op.T2T = op.T2T_own.p;
     op.xps = nX; op.tps = nT2; op.ips = nInP; op.t2tps = nT2T; op.lo = lo;
@@ -602,7 +604,7 @@ static void assemble_slice(Job &J, Prec p, int occ, void *slot, double *tmp64, h
   HIPCHK(launch_gemm_tn(g, s));
   if (p == Prec::F32) HIPCHK(launch_to_f32(tmp64, (float *)slot, n, s));
   if (p == Prec::BF16X3 || p == Prec::BF16X2)
-    HIPCHK(launch_to_bf16_parts(tmp64, (uint16_t *)slot, n, 3, s));
+    HIPCHK(launch_to_bf16_parts(tmp64, (uint16_t *)slot, n, nparts(p), s));
   if (p == Prec::FP16X2)
     HIPCHK(launch_to_f16_parts(tmp64, (uint16_t *)slot, n, J.op[(int)Prec::FP16X2].sigma_x, s));
 }
@@ -676,7 +678,7 @@ static void assemble_k_block(Job &J, int p, int q, double *dst, hipStream_t s) {
 void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double *per_triple,
                  te_stats *st, const SplitOut *split) {
   auto t0 = std::chrono::steady_clock::now();
-  const int pslot = (p == Prec::BF16X2) ? (int)Prec::BF16X3 : (int)p;
+  const int pslot = (int)p;
   if (J.xc.pslot >= 0 && J.xc.pslot != pslot) {   // slices of another precision
     HIPCHK(hipStreamSynchronize(J.s_main));
     if (J.s_aux) HIPCHK(hipStreamSynchronize(J.s_aux));
@@ -1015,7 +1017,7 @@ size_t job_footprint(int o, int v, int naux, Prec p) {
   if (p == Prec::F32) b += 4 * (nX + nT2 + nIn);
   if (p == Prec::BF16X3 || p == Prec::BF16X2 || p == Prec::FP16X2) {
     const size_t LO = (O + 7) / 8 * 8;
-    b += (p == Prec::FP16X2 ? 4 : 6) * (nX + nT2 + O * VP * O * LO + O * VP * VP * LO);
+    b += (p == Prec::BF16X3 ? 6 : 4) * (nX + nT2 + O * VP * O * LO + O * VP * VP * LO);
   }
   return b + 32 * 256;
 }

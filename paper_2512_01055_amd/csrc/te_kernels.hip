@@ -601,7 +601,8 @@ hipError_t launch_panel(Prec p, const double *stg, void *col, void *row, int o, 
                                                         o, v, vp, lo, 2, sigma);
   else
     panel_kernel<uint16_t><<<blocks_for(n), WG, 0, s>>>(stg, (uint16_t *)col, (uint16_t *)row,
-                                                        o, v, vp, lo, 3, 0.0);
+                                                        o, v, vp, lo,
+                                                        p == Prec::BF16X2 ? 2 : 3, 0.0);
   return hipGetLastError();
 }
 

@@ -307,7 +307,7 @@ ServerImpl::Launch ServerImpl::launch_round() {
   for (int q = 0; q < n; ++q) {
     SJob *j = picks[q].j;
     Job &J = *j->job;
-    const Operands &op = J.op[(P == Prec::BF16X2) ? (int)Prec::BF16X3 : (int)P];
+    const Operands &op = J.op[(int)P];
     const long t = picks[q].t;
     const int i = j->trip[3 * t], jj = j->trip[3 * t + 1], k = j->trip[3 * t + 2];
     const size_t vp = J.vp, vp3 = vp * vp * vp;
