@@ -139,10 +139,11 @@ typedef struct te_job_s *te_job;
  * device layouts). Host arrays are copied before the call returns; device
  * arrays are read during the call and may be freed afterwards, except t2,
  * which is borrowed (kept in use until te_free) when it is in device memory
- * and v is a multiple of 8.
- * Errors: TE_EINVAL for o < 1, v < 1, naux < 0, NULL required pointers or
- * (validate) bad values; TE_ENOMEM when the staged footprint exceeds the
- * budget; TE_EDEVICE for HIP failures. */
+ * and v is a multiple of 8, or when cfg->t2_host is set (host t2).
+ * Errors: TE_EINVAL for o < 1, v < 1, v > 8184, naux < 0, NULL required
+ * pointers, an inconsistent configuration or (validate) bad values;
+ * TE_ENOMEM when the staged footprint exceeds the budget; TE_EDEVICE for HIP
+ * failures. */
 te_status te_init(const te_problem *prob, const te_config *cfg, te_job *out);
 
 /* Evaluate E(T) over all occupied triples i<=j<=k (i=j=k contribute zero and
@@ -150,8 +151,8 @@ te_status te_init(const te_problem *prob, const te_config *cfg, te_job *out);
  * the weighted partial of each triple in the order of te_triple_list.
  * The result is bitwise reproducible for a given problem and precision.
  * The first call in a reduced precision converts the operands and keeps the
- * copy for later calls; a call in the other reduced precision (FP32 versus
- * the BF16 modes) releases it first, so a job holds at most one such copy. */
+ * copy for later calls; a call in another reduced precision releases it
+ * first, so a job holds at most one such copy. */
 te_status te_energy(te_job job, te_precision prec, double *e_t, double *per_triple,
                     te_stats *st);
 
