@@ -178,3 +178,36 @@ def test_checkpoint_scan_rejects_other_problems(tmp_path):
     with pytest.raises(te.TeError) as ei:
         te.checkpoint_scan(str(p), o, v, naux, "bf16x3", chunk, 5)
     assert ei.value.status == te.EINVAL
+
+
+def test_header_is_c99_and_library_links_from_c(tmp_path):
+    """include/te.h is plain C; a C program links against libte.so and calls
+    the entry points that need no device."""
+    if not os.path.exists(te.LIB_PATH):
+        pytest.skip("libte.so not built")
+    src = tmp_path / "use_te.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "te.h"
+int main(void) {
+  int32_t ijk[3 * 16];
+  te_stats st;
+  te_config cfg = {0};
+  (void)st; (void)cfg;
+  if (te_num_triples(4) != 16) return 1;
+  if (te_triple_list(4, ijk) != TE_OK || ijk[0] != 0 || ijk[2] != 1) return 2;
+  if (te_flops_per_triple(40, 400) != 12.0 * 400 * 400 * 400 * 440) return 3;
+  if (te_init(NULL, NULL, NULL) != TE_EINVAL) return 4;
+  printf("%s\n", te_strerror(TE_EIO));
+  return 0;
+}
+''')
+    exe = tmp_path / "use_te"
+    libdir = os.path.dirname(te.LIB_PATH)
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-pedantic", str(src),
+                        f"-I{os.path.join(ROOT, 'include')}", f"-L{libdir}", "-lte",
+                        f"-Wl,-rpath,{libdir}", "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    assert "checkpoint" in r.stdout
