@@ -367,6 +367,16 @@ def test_checkpointed_run_resumes_to_the_same_bits(tmp_path):
         with pytest.raises(te.TeError) as ei:
             job.energy_checkpointed("fp64", b, chunk=9, tag=8)
         assert ei.value.status == te.EINVAL and os.path.getsize(b) == size
+        H4, H5, h4, h5, _ = job.energy_terms("fp16x2")
+    # the same run with t2 in host memory and FP16 parts: per-triple parts
+    # bitwise those of the resident job, checkpointed sums to rounding
+    with te.Job(P, device=0, t2_host=True, x_cache_slices=4) as job:
+        _, _, g4, g5, _ = job.energy_terms("fp16x2")
+        assert np.array_equal(g4, h4) and np.array_equal(g5, h5)
+        done, E, E4, E5, st = job.energy_checkpointed("fp16x2", str(tmp_path / "c.ckpt"),
+                                                      chunk=20)
+        assert done and st["n_triples"] == n
+        assert abs(E4 - H4) <= 1e-13 * abs(H4) and abs(E5 - H5) <= 1e-12 * abs(H4)
 
 
 @pytest.mark.parametrize("shape", [(9, 48, 40, 28, 3), (7, 61, 30, 18, 5)], ids=["o9v48", "o7v61"])
