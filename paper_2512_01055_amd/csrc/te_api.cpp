@@ -728,7 +728,7 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
   Plan P;
   size_t slot_bytes = 0;
   // a slot: the (vv|vo) slice, then (host t2) the column panel and the row
-  // panel (FP64, FP32) or row form (BF16 parts) of its occupied index
+  // panel (FP64, FP32) or row form (16-bit parts) of its occupied index
   const size_t vp2 = (size_t)vp * vp;
   const size_t x_bytes = vp3 * es * (size_t)nparts(p);
   const size_t col_bytes = J.t2h ? (size_t)o * vp2 * es * nparts(p) : 0;

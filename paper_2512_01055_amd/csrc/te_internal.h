@@ -27,7 +27,7 @@ struct WItem {
   // (elements of the operand type; blocks are [vp][vp]):
   //   column panel   block t2[p][q_x] at Tc[x] + p * tcs
   //   row panel      block t2[q_x][l] at Tr[x] + l * trs   (FP64 / FP32 modes)
-  //   row form       t_{q_x l}^{yz}  at Tt[x] + (y vp + z) lo + l (BF16 modes)
+  //   row form       t_{q_x l}^{yz}  at Tt[x] + (y vp + z) lo + l (16-bit modes)
   // A resident t2 [part][o][o][vp][vp] gives tcs = o vp^2, trs = vp^2; panels
   // copied into a cache slot give tcs = trs = vp^2. Part p of a column panel
   // (or of the occupied segments' row panel) at + p * tcps, of the row form
@@ -37,7 +37,7 @@ struct WItem {
   size_t xps, tcs, trs, tcps, ips, t2tps;
   int lo;          // length of the occupied rows of In and the row form: o in
                    // FP64 and FP32 modes, o rounded up to 8 (zero padded) in
-                   // BF16 modes
+                   // 16-bit modes
   void *W;         // three boxed W arrays of vp^3 each (FP64 or FP32)
   float scale;     // FP16 parts: 1 / (sigma_X sigma_T), applied to W; else 1
   int o, vp, i, j, k;

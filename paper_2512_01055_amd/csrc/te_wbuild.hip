@@ -149,7 +149,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
     if (su.om[s] == 0) { TO[s] = reinterpret_cast<const T *>(w.Tr[su.op[s]]); ksO[s] = (long)w.trs; }
     else               { TO[s] = reinterpret_cast<const T *>(w.Tc[su.op[s]]); ksO[s] = (long)w.tcs; }
   }
-  // BF16 modes: occupied-segment rows of T2T (t_{p l}^{yz} with l last), read
+  // 16-bit modes: occupied-segment rows of T2T (t_{p l}^{yz} with l last), read
   // like the X rows; om = 1 takes the swapped pair (t_{l p}^{yz} = t_{p l}^{zy})
   const int lo = w.lo;
   const T *TT0 = reinterpret_cast<const T *>(w.Tt[su.op[0]]);
