@@ -56,8 +56,9 @@ __device__ inline Setup make_setup(int g, int i, int j, int k) {
 
 // NB: 16-column blocks per tile (BN = 16 NB); WM: 16-row blocks per wave
 // (BM = 4 waves x 16 WM rows). The register budget asks for three waves per
-// SIMD; that is what the two-part BF16 tiles' LDS allows (the other modes are
-// held to two by LDS and are not constrained by it).
+// SIMD. The two LDS stages hold 2 NP (BM + BN) KT elements: 52 KiB at
+// BM = 128, BN = 80 for FP64, FP32 and the two-part 16-bit modes, so three
+// workgroups share a CU's 160 KiB; three BF16 parts (78 KiB) fit two.
 template <Prec P, int NB, int WM>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wbuild_kernel(const WItem *__restrict__ items,
                                                     const int *__restrict__ tile_item,
@@ -396,12 +397,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
 }  // namespace
 
 // ------------------------------------------------------------ launchers
-// Tile shape per precision: rows per wave (WM) and the column-block count
-// NB in [4, 8] that minimises padded waste of the lone index (larger NB on
-// ties).
-WConfig wbuild_config(Prec p, int vp) {
+// Tile shape: two 16-row blocks per wave in every precision, and the
+// column-block count NB in [4, 8] that minimises padded waste of the lone
+// index (larger NB on ties).
+WConfig wbuild_config(Prec, int vp) {
   WConfig c;
-  c.wm = (p == Prec::F64) ? 2 : 2;
+  c.wm = 2;
   int best = 8;
   long best_w = -1;
   for (int nb = 8; nb >= 4; --nb) {
