@@ -36,7 +36,7 @@ typedef enum te_status {
   TE_EINVAL = -1,     /* bad argument (sizes, NULL pointers, bad values)   */
   TE_ENOMEM = -2,     /* the job cannot fit in the HBM budget              */
   TE_EDEVICE = -3,    /* a HIP runtime call failed                         */
-  TE_EBUSY = -4,      /* the server is shutting down / queue full          */
+  TE_EBUSY = -4,      /* server shutting down / queue full / file in use   */
   TE_ENOTFOUND = -5,  /* unknown or already-collected ticket               */
   TE_ECANCELED = -6,  /* the server was destroyed before the job ran       */
   TE_EIO = -7         /* reading or writing a checkpoint file failed       */
@@ -191,7 +191,10 @@ te_status te_energy_terms(te_job job, te_precision prec, const int32_t *ijk, int
  * taken in triple order with compensation on the host: an interrupted and
  * resumed run gives the same bits as one that ran through. Returns
  * TE_PENDING while chunks remain (outputs untouched). st (optional)
- * describes the work of this call only. File errors: TE_EIO. */
+ * describes the work of this call only. The call holds an exclusive
+ * advisory lock (flock) on the file while it runs: a second call on the same
+ * file, from this or another process, returns TE_EBUSY at once and leaves
+ * the file as it is. File errors: TE_EIO. */
 te_status te_energy_checkpointed(te_job job, te_precision prec, const char *path, uint64_t tag,
                                  int64_t chunk, int64_t max_chunks, double *e_t,
                                  double *e4_sum, double *e5_sum, te_stats *st);

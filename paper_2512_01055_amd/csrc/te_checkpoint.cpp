@@ -10,8 +10,11 @@
 //   record  int64 first triple, int64 count, double e4[count],
 //           double e5[count], uint64 FNV-1a of the record's other bytes
 // A record is written whole and flushed to disk before the next chunk
-// starts; a torn last record fails its checksum and is recomputed.
+// starts; a torn last record fails its checksum and is recomputed. A writer
+// holds an exclusive advisory lock on the file, so that a second run on the
+// same checkpoint is turned away instead of interleaving its records.
 #include <fcntl.h>
+#include <sys/file.h>
 #include <sys/stat.h>
 #include <unistd.h>
 
@@ -185,6 +188,12 @@ te_status te_energy_checkpointed(te_job job, te_precision prec, const char *path
   Fd f;
   f.fd = ::open(path, O_RDWR | O_CREAT | O_CLOEXEC, 0644);
   if (f.fd < 0) io_fail("open", path);
+  while (::flock(f.fd, LOCK_EX | LOCK_NB) != 0) {
+    if (errno == EINTR) continue;
+    if (errno == EWOULDBLOCK)
+      return set_error(TE_EBUSY, std::string("checkpoint ") + path + " is in use by another run");
+    io_fail("lock", path);
+  }
   struct stat sb;
   if (::fstat(f.fd, &sb) != 0) io_fail("stat", path);
   std::vector<char> done((size_t)nchunks, 0);

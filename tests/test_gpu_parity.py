@@ -367,6 +367,15 @@ def test_checkpointed_run_resumes_to_the_same_bits(tmp_path):
         with pytest.raises(te.TeError) as ei:
             job.energy_checkpointed("fp64", b, chunk=9, tag=8)
         assert ei.value.status == te.EINVAL and os.path.getsize(b) == size
+        # a file another run holds is turned away before it is read or changed
+        import fcntl
+        with open(b, "rb") as holder:
+            fcntl.flock(holder, fcntl.LOCK_EX)
+            with pytest.raises(te.TeError) as ei:
+                job.energy_checkpointed("fp64", b, chunk=9, tag=7)
+            assert ei.value.status == te.EBUSY and os.path.getsize(b) == size
+        done, E_d, *_ = job.energy_checkpointed("fp64", b, chunk=9, tag=7)
+        assert done and E_d == E
         H4, H5, h4, h5, _ = job.energy_terms("fp16x2")
     # the same run with t2 in host memory and FP16 parts: per-triple parts
     # bitwise those of the resident job, checkpointed sums to rounding
