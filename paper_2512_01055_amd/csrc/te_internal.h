@@ -84,8 +84,10 @@ struct GemmTN {
   double alpha;
 };
 
-// Launchers (te_kernels.hip). All return the hipError_t of the launch.
-// W-build tile shape: BM = 64 wm rows (virtual pairs), BN = 16 nb columns.
+// Launchers (W build in te_wbuild.hip, the rest in te_kernels.hip). All
+// return the hipError_t of the launch.
+// W-build tile shape: BM = 64 wm rows (virtual pairs), BN = 16 nb columns;
+// wm = 2 is the only row count built.
 struct WConfig {
   int nb = 5, wm = 2;
   int bm() const { return 64 * wm; }

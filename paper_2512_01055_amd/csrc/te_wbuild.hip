@@ -433,11 +433,8 @@ static hipError_t launch_wb_pw(const WItem *d_items, const int *d_tile_item, int
 template <Prec P>
 static hipError_t launch_wb_p(const WItem *d_items, const int *d_tile_item, int tiles_per_item,
                               long total, WConfig c, hipStream_t s) {
-  if (c.wm == 2) return launch_wb_pw<P, 2>(d_items, d_tile_item, tiles_per_item, total, c.nb, s);
-  if constexpr (P != Prec::BF16X3) {  // three BF16 parts of a 256-row tile exceed LDS
-    if (c.wm == 4) return launch_wb_pw<P, 4>(d_items, d_tile_item, tiles_per_item, total, c.nb, s);
-  }
-  return hipErrorInvalidValue;
+  if (c.wm != 2) return hipErrorInvalidValue;  // the only row count instantiated
+  return launch_wb_pw<P, 2>(d_items, d_tile_item, tiles_per_item, total, c.nb, s);
 }
 
 hipError_t launch_wbuild(Prec p, const WItem *d_items, const int *d_tile_item, int nitems,
