@@ -34,6 +34,8 @@ __global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ it
                                                     const int *__restrict__ blk_item,
                                                     int blks_per_item, long total) {
   __shared__ double box[6 * BX_S];
+  __shared__ double kst[6 * 3 * BOX * BOX];
+  __shared__ double vst[4 * 3 * BOX];
   __shared__ double red[2 * (WG / 64)];
   const int tid = threadIdx.x;
   const long bid = blockIdx.x;
@@ -81,15 +83,48 @@ __global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ it
       wv[u] = ((double)gld(W0 + base) + (double)gld(W1 + base)) + (double)gld(W2 + base);
     }
   }
+  // The inputs of V and D go to LDS in the same pass: per slot the 8 x 8
+  // blocks of (jb|kc), (ia|kc) and (ia|jb) it reads (kst[s][0..2][row][col]),
+  // and per box index T[m] the eight t1 entries of rows i, j, k and the eight
+  // virtual orbital energies (vst[0..3][m][x]). Box indices are below vp / 8,
+  // so every one of these loads is inside the padded arrays.
+  // Thread tid < KB holds value tid of every slot's K blocks; the slot loop is
+  // unrolled and the box index chosen by selects, so that no private array
+  // is indexed per lane.
+  constexpr int KB = 3 * BOX * BOX, NV = 4 * 3 * BOX;
+  double kv[6];
+  {
+    const int mat = tid >> 6, p = (tid >> 3) & 7, r = tid & 7;
+    const double *Km = mat == 0 ? e.Kjk : (mat == 1 ? e.Kik : e.Kij);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      kv[s] = 0.0;
+      if (tid < KB && canon[s] == s) {
+        const int rb = mat == 0 ? bx[s][1] : bx[s][0];   // rows: b, a, a
+        const int cb = mat == 2 ? bx[s][1] : bx[s][2];   // columns: c, c, b
+        kv[s] = gld(Km + (long)(rb * BOX + p) * e.kld + cb * BOX + r);
+      }
+    }
+  }
+  double tv = 0.0;
+  if (tid < NV) {
+    const int w = tid / (3 * BOX), m = (tid / BOX) % 3;
+    const int x = (m == 0 ? T[0] : (m == 1 ? T[1] : T[2])) * BOX + (tid & 7);
+    tv = w == 3 ? gld(e.ev + x) : gld(e.t1 + (long)(w == 0 ? i : (w == 1 ? j : k)) * vp + x);
+  }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int s = u >> 1, r = tid + WG * (u & 1);
     if (canon[s] == s) box[s * BX_S + bxi(r >> 6, (r >> 3) & 7, r & 7)] = wv[u];
   }
+  if (tid < KB) {
+#pragma unroll
+    for (int s = 0; s < 6; ++s) kst[s * KB + tid] = kv[s];
+  }
+  if (tid < NV) vst[tid] = tv;
   __syncthreads();
 
   const double eijk = (e.eo[i] + e.eo[j]) + e.eo[k];
-  const double *t1i = e.t1 + (long)i * vp, *t1j = e.t1 + (long)j * vp, *t1k = e.t1 + (long)k * vp;
   double acc4 = 0.0, acc5 = 0.0;   // W Z / D and V Z / D (E[4] and E[5] parts)
 #pragma unroll 1
   for (int s = 0; s < 6; ++s) {
@@ -99,6 +134,9 @@ __global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ it
     const int sd = canon[c_comp[s][1]] * BX_S;  // (a,c,b)
     const int se = canon[c_comp[s][2]] * BX_S;  // (b,a,c)
     const int sf = canon[c_comp[s][4]] * BX_S;  // (c,b,a)
+    const double *ks = kst + s * KB;
+    const double *va = vst + c_perm[s][0] * BOX, *vb = vst + c_perm[s][1] * BOX,
+                 *vc = vst + c_perm[s][2] * BOX;
     for (int r = tid; r < BOX3; r += WG) {
       const int x0 = r >> 6, x1 = (r >> 3) & 7, x2 = r & 7;
       const int a = bx[s][0] * 8 + x0, b = bx[s][1] * 8 + x1, c = bx[s][2] * 8 + x2;
@@ -108,10 +146,10 @@ __global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ it
                          - 2.0 * box[sd + bxi(x0, x2, x1)] - 2.0 * box[se + bxi(x1, x0, x2)]
                          - 2.0 * box[sf + bxi(x2, x1, x0)];
         // singles term (Eq. 3): t_i^a (jb|kc) + t_j^b (ia|kc) + t_k^c (ia|jb)
-        const double vt = gld(t1i + a) * gld(e.Kjk + b * e.kld + c)
-                        + gld(t1j + b) * gld(e.Kik + a * e.kld + c)
-                        + gld(t1k + c) * gld(e.Kij + a * e.kld + b);
-        const double d = ((eijk - gld(e.ev + a)) - gld(e.ev + b)) - gld(e.ev + c);
+        const double vt = va[x0] * ks[x1 * BOX + x2]
+                        + vb[3 * BOX + x1] * ks[BOX * BOX + x0 * BOX + x2]
+                        + vc[6 * BOX + x2] * ks[2 * BOX * BOX + x0 * BOX + x1];
+        const double d = ((eijk - va[9 * BOX + x0]) - vb[9 * BOX + x1]) - vc[9 * BOX + x2];
         const double q = z / d;
         acc4 += w0 * q;
         acc5 += vt * q;
