@@ -211,3 +211,43 @@ int main(void) {
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, (r.returncode, r.stderr)
     assert "checkpoint" in r.stdout
+
+
+def test_checkpoint_scan_survives_corruption(tmp_path):
+    """Random byte flips, truncations and appended garbage never crash the
+    reader: it answers OK or EINVAL, and never counts more chunks than the
+    intact records of the file hold."""
+    o, v, naux, chunk, tag = 5, 12, 9, 4, 3
+    head, n = _ckpt_header(o, v, naux, 0, tag, chunk)
+    total = (n + chunk - 1) // chunk
+    recs = [_ckpt_record(f, [1.0 + f + q for q in range(min(chunk, n - f))],
+                         [2.0 - q for q in range(min(chunk, n - f))]) for f in range(0, n, chunk)]
+    good = head + b"".join(recs)
+    p = tmp_path / "fuzz.ckpt"
+    rng = np.random.default_rng(11)
+    for trial in range(300):
+        b = bytearray(good)
+        kind = trial % 3
+        if kind == 0:
+            for _ in range(int(rng.integers(1, 4))):
+                b[int(rng.integers(len(b)))] ^= int(rng.integers(1, 256))
+        elif kind == 1:
+            b = b[:int(rng.integers(len(b) + 1))]
+        else:
+            b += rng.integers(0, 256, int(rng.integers(1, 200)), dtype=np.uint8).tobytes()
+        p.write_bytes(bytes(b))
+        done, tot = C.c_int64(-1), C.c_int64(-1)
+        s = te.lib().te_checkpoint_scan(str(p).encode(), o, v, naux, 0, tag, chunk,
+                                        C.byref(done), C.byref(tot))
+        assert s in (te.OK, te.EINVAL), (trial, s)
+        if s == te.OK:
+            assert tot.value == total and 0 <= done.value <= total
+            # records are checksummed: a scan never counts a record whose bytes changed
+            intact = 0
+            off = len(head)
+            for r in recs:
+                if bytes(b[off:off + len(r)]) != r:
+                    break
+                intact += 1
+                off += len(r)
+            assert done.value == intact, (trial, done.value, intact)
