@@ -11,7 +11,13 @@ factors of the paper's molecules, which are not available:
   (left unsorted);
 * DF factors B^Q_pq ~ N(0, b_std^2), symmetric in the orbital pair: the
   elements with p <= q are drawn i.i.d. and mirrored, so every element keeps
-  the same spread;
+  the same spread. Each draw is rounded to a multiple of 2^-20 (a relative
+  change of ~1e-5 at b_std = 0.05). Products of two such values are
+  multiples of 2^-40, and while max|B|^2 naux < 2^13 every partial sum of
+  (pq|rs) = sum_Q B^Q_pq B^Q_rs is a multiple of 2^-40 below 2^13, which
+  FP64 holds exactly: every integral, and so the doubles below, come out
+  bitwise the same whatever the summation order (numpy or torch, host or
+  device, any BLAS);
 * MP2-like doubles t_ij^ab = (ia|jb) / (e_i + e_j - e_a - e_b) with
   (ia|jb) = sum_Q B^Q_ia B^Q_jb, so t_ij^ab = t_ji^ba holds exactly;
 * singles t_i^a ~ N(0, t1_std^2).
@@ -53,15 +59,35 @@ LARGE = (40, 400, 1200, 3)      # the throughput workload
 HUGE = (100, 800, 2400, 5)      # (vv|vo) assembled on the fly
 
 
+# Factor values are drawn on this grid (see the module docstring).
+GRID = 2.0 ** 20
+
+
+def _on_grid(x: np.ndarray) -> np.ndarray:
+    """x rounded to the nearest multiple of 1 / GRID (in place)."""
+    x *= GRID
+    np.rint(x, out=x)
+    x *= 1.0 / GRID
+    return x
+
+
 def _sym_normal(rng: np.random.Generator, naux: int, n: int, std: float) -> np.ndarray:
     """naux symmetric n x n matrices; p<=q drawn i.i.d., mirrored below."""
     out = np.empty((naux, n, n))
     iu = np.triu_indices(n)
     for q in range(naux):
         m = np.zeros((n, n))
-        m[iu] = rng.standard_normal(len(iu[0])) * std
+        m[iu] = _on_grid(rng.standard_normal(len(iu[0])) * std)
         out[q] = m + np.triu(m, 1).T
     return out
+
+
+def _check_exact(naux: int, *factors: np.ndarray) -> None:
+    """The factor integrals are exact in FP64 only while every partial sum
+    stays below 2^13 (2^53 grid units of 2^-40)."""
+    m = max(float(np.abs(f).max()) for f in factors if f.size)
+    if m * m * naux >= 2.0 ** 13:
+        raise ValueError(f"factors too large for exact integrals: max|B| = {m}, naux = {naux}")
 
 
 def make_problem(o: int, v: int, naux: int, seed: int, *, b_std: float = 0.05,
@@ -73,8 +99,9 @@ def make_problem(o: int, v: int, naux: int, seed: int, *, b_std: float = 0.05,
     eps_occ = rng.uniform(-1.5, -0.3, o)
     eps_vir = rng.uniform(0.1, 3.0, v)
     B_oo = _sym_normal(rng, naux, o, b_std)
-    B_ov = rng.standard_normal((naux, o, v)) * b_std
+    B_ov = _on_grid(rng.standard_normal((naux, o, v)) * b_std)
     B_vv = _sym_normal(rng, naux, v, b_std)
+    _check_exact(naux, B_oo, B_ov, B_vv)
     t1 = rng.standard_normal((o, v)) * t1_std
     if not with_t1:
         t1[:] = 0.0
@@ -129,8 +156,9 @@ def draw_factors(o: int, v: int, naux: int, seed: int, *, b_std: float = 0.05,
     eps_occ = rng.uniform(-1.5, -0.3, o)
     eps_vir = rng.uniform(0.1, 3.0, v)
     B_oo = _sym_normal(rng, naux, o, b_std)
-    B_ov = rng.standard_normal((naux, o, v)) * b_std
+    B_ov = _on_grid(rng.standard_normal((naux, o, v)) * b_std)
     B_vv = _sym_normal(rng, naux, v, b_std)
+    _check_exact(naux, B_oo, B_ov, B_vv)
     t1 = rng.standard_normal((o, v)) * t1_std
     return eps_occ, eps_vir, t1, B_oo, B_ov, B_vv
 
@@ -163,9 +191,12 @@ def make_problem_device(o: int, v: int, naux: int, seed: int, device="cuda:0", *
                         b_std: float = 0.05, t1_std: float = 1e-3):
     """make_problem with the doubles formed on the device (torch, FP64), for
     sizes whose o^2 v^2 array is too large to build on the host. The draws
-    are identical to make_problem's; t2 differs from the host version only by
-    the rounding order of its (ia|jb) sums. Returns an object with torch
-    device tensors eps_occ, eps_vir, t1, t2, B_oo, B_ov, B_vv and o, v, naux."""
+    are identical to make_problem's, and since the factors sit on the exact
+    grid, so is t2, bit for bit: (ia|jb) is exact in any summation order,
+    and the symmetrisation, the denominators and the one division are the
+    same IEEE operations as on the host. Returns an object with torch
+    tensors (on `device`) eps_occ, eps_vir, t1, t2, B_oo, B_ov, B_vv and
+    o, v, naux."""
     import torch
     eo, ev, t1, B_oo, B_ov, B_vv = draw_factors(o, v, naux, seed, b_std=b_std, t1_std=t1_std)
     dev = torch.device(device)
@@ -186,6 +217,7 @@ def make_problem_device(o: int, v: int, naux: int, seed: int, device="cuda:0", *
         den = (e_o[i] + e_o)[:, None, None] - (e_v[:, None] + e_v[None, :])[None]
         t2[i] /= den
     out.t2 = t2
-    torch.cuda.synchronize()
-    torch.cuda.empty_cache()     # return the temporaries to the device
+    if dev.type == "cuda":
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()     # return the temporaries to the device
     return out

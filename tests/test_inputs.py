@@ -44,3 +44,46 @@ def test_triple_lists():
     pos = [allt.index(tuple(x)) for x in s]
     assert len(s) == 8 and pos == sorted(set(pos))
     assert any(i == j < k for i, j, k in s) and any(i < j == k for i, j, k in s)
+
+
+def test_factors_sit_on_the_exact_grid():
+    P = inputs.make_problem(6, 20, 40, 31)
+    for B in (P.B_oo, P.B_ov, P.B_vv):
+        scaled = B * inputs.GRID
+        assert np.array_equal(scaled, np.rint(scaled))
+    with np.testing.assert_raises(ValueError):     # sums could leave the exact range
+        inputs.make_problem(2, 3, 40, 31, b_std=20.0)
+
+
+def test_integrals_do_not_depend_on_summation_order():
+    """(ia|jb) from a BLAS product, from a left-to-right loop and from a
+    right-to-left loop are the same bits, and equal the exactly rounded sum."""
+    import math
+    P = inputs.make_problem(3, 9, 50, 32)
+    L = P.B_ov.reshape(P.naux, -1)
+    blas = L.T @ L
+    fwd = np.zeros_like(blas)
+    for q in range(P.naux):
+        fwd += np.outer(L[q], L[q])
+    bwd = np.zeros_like(blas)
+    for q in reversed(range(P.naux)):
+        bwd += np.outer(L[q], L[q])
+    assert np.array_equal(blas, fwd) and np.array_equal(blas, bwd)
+    for (x, y) in ((0, 0), (4, 17), (26, 3)):
+        assert blas[x, y] == math.fsum(L[:, x] * L[:, y])
+
+
+def test_doubles_formed_three_ways_are_bitwise_equal():
+    """The host recipe, the on-demand pairs and the torch formation used for
+    problems too large for host memory (run here on the CPU) agree bit for
+    bit."""
+    o, v, naux, seed = 5, 24, 60, 33
+    P = inputs.make_problem(o, v, naux, seed)
+    lazy = inputs.LazyDoubles(P.eps_occ, P.eps_vir, P.B_ov)
+    for (i, j) in ((0, 0), (1, 3), (4, 2)):
+        assert np.array_equal(lazy[i, j], P.t2[i, j])
+    assert np.array_equal(lazy[:, 2], P.t2[:, 2])
+    D = inputs.make_problem_device(o, v, naux, seed, device="cpu")
+    assert np.array_equal(D.t2.numpy(), P.t2)
+    for n in ("eps_occ", "eps_vir", "t1", "B_oo", "B_ov", "B_vv"):
+        assert np.array_equal(getattr(D, n).numpy(), getattr(P, n))
