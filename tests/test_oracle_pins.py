@@ -241,3 +241,35 @@ def test_planted_mistake_is_caught(name, monkeypatch):
         if not math.isfinite(E) or abs(E - ref) > 1e-6 * abs(ref):
             caught = True
     assert caught, f"mutation {name} slipped past the spin-orbital pin"
+
+
+def test_compensated_sum_of_large_arrays():
+    """Above 2^20 elements (every triple with v >= 102) the oracle's per-triple
+    sum adds 4096-element blocks in order and then sums the block totals
+    exactly. Against math.fsum of the whole array (exactly rounded) it must
+    stay within the error bound of one block's sequential sum, 4096 u sum|x|.
+    The array cancels heavily, has a ragged last block holding its largest
+    element, and every element is far above the bound, so a block, an
+    element or the tail left out is caught (the last check plants that)."""
+    rng = np.random.default_rng(5)
+    n = (1 << 21) + 1237
+    x = rng.choice([-1.0, 1.0], n) * rng.uniform(1e-3, 2e-3, n)
+    big = rng.choice(n - 1, 64, replace=False)
+    x[big[:32]] = rng.uniform(1e2, 1e3, 32)         # large values that cancel in pairs
+    x[big[32:]] = -x[big[:32]]
+    x[-1] = 2.5e3
+    exact = math.fsum(x.tolist())
+    bound = 4096 * 2.0 ** -53 * float(np.abs(x).sum())
+    assert np.abs(x).min() > 1e3 * bound
+    got = cs._fsum(x)
+    assert abs(got - exact) <= bound
+    # the same with the array length a multiple of the block size
+    y = x[:1 << 21]
+    assert abs(cs._fsum(y) - math.fsum(y.tolist())) <= bound
+    # small arrays take math.fsum itself: exactly rounded
+    z = x[:1 << 20]
+    assert cs._fsum(z) == math.fsum(z.tolist())
+    # planted mistake: the ragged last block dropped
+    full = n // 4096 * 4096
+    dropped = math.fsum(x[:full].reshape(-1, 4096).sum(1).tolist())
+    assert abs(dropped - exact) > 1e3 * bound
