@@ -135,9 +135,13 @@ typedef struct te_stats {
 
 typedef struct te_job_s *te_job;
 
-/* Stage a problem on the device (integral assembly from the factors, padded
- * device layouts). Host arrays are copied before the call returns; device
- * arrays are read during the call and may be freed afterwards, except t2,
+/* Stage a problem on the device: the integrals of Eqs. 2 and 3 assembled
+ * from the factors as Eq. 6 defines them, (pq|rs) = sum_Q B^Q_pq B^Q_rs --
+ * (ia|jb) for the singles term, (ia|jk) for the occupied term of Eq. 2 and,
+ * unless they are assembled on the fly, every (ia|bc) slice -- and padded
+ * device layouts. Host arrays are copied before the call returns; device
+ * arrays are read during the call and may be freed afterwards (in the
+ * on-the-fly mode the job keeps its own copies of B_ov and B_vv), except t2,
  * which is borrowed (kept in use until te_free) when it is in device memory
  * and v is a multiple of 8, or when cfg->t2_host is set (host t2).
  * Errors: TE_EINVAL for o < 1, v < 1, v > 8184, naux < 0, NULL required
@@ -146,9 +150,14 @@ typedef struct te_job_s *te_job;
  * failures. */
 te_status te_init(const te_problem *prob, const te_config *cfg, te_job *out);
 
-/* Evaluate E(T) over all occupied triples i<=j<=k (i=j=k contribute zero and
- * are skipped). Blocks until done. `per_triple` (host, optional) receives
- * the weighted partial of each triple in the order of te_triple_list.
+/* Evaluate E(T) of Eq. 1 over all occupied triples i<=j<=k (i=j=k
+ * contribute zero and are skipped), in the form that carries Eq. 1's
+ * restricted virtual sum over to the occupied labels: each triple's
+ * sum_abc (W + V) Z / D weighted by 2 - d_ij - d_jk, with W from Eq. 2
+ * summed over the permutations of Eq. 5, V from Eq. 3 and D from Eq. 4
+ * (occupied minus virtual energies). Blocks until done. `per_triple` (host,
+ * optional) receives the weighted partial of each triple in the order of
+ * te_triple_list.
  * The result is bitwise reproducible for a given problem and precision.
  * The first call in a reduced precision converts the operands and keeps the
  * copy for later calls; a call in another reduced precision releases it
@@ -242,14 +251,18 @@ typedef struct te_server_config {
 } te_server_config;
 
 te_status te_server_create(const te_server_config *cfg, te_server *out);
-/* Queues a problem in host memory (copied, or borrowed with borrow_inputs).
- * Returns TE_ENOMEM if the job could never fit the budget, TE_EBUSY if the
- * queue is full. */
+/* Queues a problem in host memory (copied, or borrowed with borrow_inputs)
+ * for the E(T) of te_energy (Eq. 1 over i<=j<=k, Eqs. 2-6) in precision
+ * `prec`; *ticket names it for te_poll / te_wait. Returns TE_ENOMEM if the
+ * job could never fit the budget, TE_EBUSY if the queue is full or the
+ * server is shutting down, TE_EDEVICE after a device failure. */
 te_status te_submit(te_server srv, const te_problem *prob, te_precision prec,
                     uint64_t *ticket);
 /* TE_PENDING while queued or running; the job's final status otherwise
- * (TE_OK with e_t and st filled in). The ticket is released by the first
- * final answer; later polls return TE_ENOTFOUND. */
+ * (TE_OK with e_t = E(T) of Eq. 1, bitwise what te_energy gives for the same
+ * problem and precision, and st filled in; st->seconds is the latency from
+ * te_submit to completion). The ticket is released by the first final
+ * answer; later polls return TE_ENOTFOUND. */
 te_status te_poll(te_server srv, uint64_t ticket, double *e_t, te_stats *st);
 /* te_poll that blocks until the job is final. */
 te_status te_wait(te_server srv, uint64_t ticket, double *e_t, te_stats *st);

@@ -282,9 +282,20 @@ static void stage(Job &J, const te_problem &P) {
   const size_t nX = (size_t)o * vp * vp * vp;
   if (J.naux > 0) {
     const int naux = J.naux;
-    J.Bov = device_view(J, P.B_ov, (size_t)naux * o * v, J.Bov_own);
+    if (J.x_resident) {
+      // read only here: device arrays are borrowed for the call
+      J.Bov = device_view(J, P.B_ov, (size_t)naux * o * v, J.Bov_own);
+      J.Bvv = device_view(J, P.B_vv, (size_t)naux * v * v, J.Bvv_own);
+    } else {
+      // on the fly, every later call assembles slices and (ov|ov) blocks
+      // from B_ov and B_vv: the job keeps its own copies, so the caller may
+      // free device arrays once te_init returns
+      copy_in(J, P.B_ov, (size_t)naux * o * v, J.Bov_own, dev);
+      copy_in(J, P.B_vv, (size_t)naux * v * v, J.Bvv_own, dev);
+      J.Bov = J.Bov_own.as<double>();
+      J.Bvv = J.Bvv_own.as<double>();
+    }
     J.Boo = device_view(J, P.B_oo, (size_t)naux * o * o, J.Boo_own);
-    J.Bvv = device_view(J, P.B_vv, (size_t)naux * v * v, J.Bvv_own);
     // |(px|yf)| <= |B_px| |B_yf| (Cauchy-Schwarz over the factor index)
     J.x_bound = std::sqrt(dev_colnorm_max(J, J.Bov, (long)o * v) *
                           dev_colnorm_max(J, J.Bvv, (long)v * v));
@@ -301,6 +312,9 @@ static void stage(Job &J, const te_problem &P) {
     HIPCHK(hipMemsetAsync(J.In.p, 0, J.In.bytes, s));
     gemm_stage(J, J.Bov, (long)o * v, J.Boo, (long)o * o, o * v, o * o, naux, v,
                (long)vp * o * o, (long)o * o, o * o, 0, 1, -1.0, J.In.as<double>());
+    HIPCHK(hipStreamSynchronize(s));
+    J.Boo_own.release();            // B_oo is not read after staging
+    J.Boo = nullptr;
     if (J.x_resident) {
       jalloc(J, J.X, nX * 8);
       std::vector<int> all(o);
@@ -308,8 +322,8 @@ static void stage(Job &J, const te_problem &P) {
       stage_df_slices(J, all.data(), o, J.X.as<double>(), (size_t)vp * vp * vp);
       HIPCHK(hipStreamSynchronize(s));
       // factors are no longer needed once every slice is resident
-      J.Bov_own.release(); J.Boo_own.release(); J.Bvv_own.release();
-      J.Bov = J.Boo = J.Bvv = nullptr;
+      J.Bov_own.release(); J.Bvv_own.release();
+      J.Bov = J.Bvv = nullptr;
     }
   } else {
     stage_padded(J, P.ovov, o, v, o, v, vp, o, vp, 1.0, J.K);
@@ -664,6 +678,32 @@ void resident_k_views(const Job &J, int i, int j, int k, EItem &e) {
   e.Kik = K + (i * vp * o + k) * vp;
   e.Kij = K + (i * vp * o + j) * vp;
   e.kld = o * vp;
+}
+
+void resident_items(const Job &J, const Operands &op, Prec p, int i, int j, int k, int mt,
+                    int nt, void *W, double *part, double *out, WItem &w, EItem &e, RItem &r) {
+  const size_t vp3 = (size_t)J.vp * J.vp * J.vp, es = elem_size(p);
+  w = WItem{};
+  w.Xs[0] = (const char *)op.X + (size_t)i * vp3 * es;
+  w.Xs[1] = (const char *)op.X + (size_t)j * vp3 * es;
+  w.Xs[2] = (const char *)op.X + (size_t)k * vp3 * es;
+  w.xps = op.xps;
+  w.In = op.In;
+  w.ips = op.ips; w.lo = op.lo; w.scale = op.scale;
+  w.W = W; w.o = J.o; w.vp = J.vp; w.i = i; w.j = j; w.k = k; w.mt = mt; w.nt = nt;
+  resident_t2_views(J, op, p, w);
+  e = EItem{};
+  resident_k_views(J, i, j, k, e);
+  e.W = W; e.t1 = J.t1.as<double>();
+  e.eo = J.eo.as<double>(); e.ev = J.ev.as<double>(); e.sext = J.sext.as<int>();
+  e.part = part;
+  e.part5 = part + J.nsext;
+  e.o = J.o; e.v = J.v; e.vp = J.vp; e.nT = J.vp / BOX; e.i = i; e.j = j; e.k = k;
+  e.nsext = J.nsext;
+  r = RItem{};
+  r.part = e.part; r.part5 = e.part5; r.out = out; r.n = J.nsext;
+  r.out4 = r.out5 = nullptr;
+  r.w = 2.0 - (i == j) - (j == k);
 }
 
 // (px|qy) for one occupied pair as a v x v block with row stride vp (Eq. 6

@@ -140,6 +140,12 @@ void resident_k_views(const Job &J, int i, int j, int k, EItem &e);
 // t2 views of a W item over the device-resident t2 (and row form) of `op`;
 // w.i, w.j, w.k must be set.
 void resident_t2_views(const Job &J, const Operands &op, Prec p, WItem &w);
+// The three launch items of triple (i, j, k) of a job whose (vv|vo) slices
+// and (ov|ov) array are resident: W build (W: its three boxed shares), energy
+// (part: 2 nsext sextet partials, E[4] then E[5]) and reduction (out: the
+// weighted per-triple result). mt, nt: tiles of the W build along M and N.
+void resident_items(const Job &J, const Operands &op, Prec p, int i, int j, int k, int mt,
+                    int nt, void *W, double *part, double *out, WItem &w, EItem &e, RItem &r);
 // Optional E[4] / E[5] outputs of run_triples (any pointer may be null).
 struct SplitOut {
   double *e4_sum = nullptr, *e5_sum = nullptr;   // sums over the listed triples

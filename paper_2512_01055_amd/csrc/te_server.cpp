@@ -144,6 +144,7 @@ struct ServerImpl {
   Launch launch_round();
   void retire();
   void finish_job(SJob *j, te_status s, const std::string &msg);
+  void fail_all(te_status s, const std::string &msg);
 };
 
 void ServerImpl::finish_job(SJob *j, te_status s, const std::string &msg) {
@@ -204,7 +205,11 @@ void ServerImpl::stage_loop(int q) {
     }
     std::lock_guard<std::mutex> lk(mu);
     j->t_staged = clk::now();
-    if (s == TE_ENOMEM && resident.size() > 1) {
+    if (!fatal.empty() && s == TE_OK) {   // the server failed while this job staged
+      s = TE_EDEVICE;
+      msg = fatal;
+    }
+    if (s == TE_ENOMEM && resident.size() > 1 && fatal.empty()) {
       // the arena is fragmented by other resident jobs: retry after one retires
       resident.remove(j);
       j->eout.release();
@@ -425,12 +430,41 @@ void ServerImpl::sched_loop() {
       if (l == Launch::NoWork) cv.wait_for(lk, std::chrono::microseconds(200));
     }
   } catch (const Fail &f) {
-    std::lock_guard<std::mutex> lk(mu);
-    fatal = f.msg;
-    for (auto &kv : jobs)
-      if (kv.second->state != JS::Done) finish_job(kv.second.get(), f.s, f.msg);
-    cv_done.notify_all();
+    fail_all(f.s, f.msg);
   }
+}
+
+// A device failure ends the server: no more staging or admission, the
+// device work in flight drains before any job's memory is released, and
+// every job ends with the error. A job a stager is still staging is left to
+// that stager, which finishes it (stage_loop checks `fatal`) so that no
+// caller can collect and free it under the stager's feet.
+void ServerImpl::fail_all(te_status s, const std::string &msg) {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    fatal = msg;
+    stop = true;
+    queue.clear();
+  }
+  cv.notify_all();
+  (void)hipSetDevice(device);
+  if (s_w) (void)hipStreamSynchronize(s_w);
+  if (s_e) (void)hipStreamSynchronize(s_e);
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto it = resident.begin(); it != resident.end();) {
+    SJob *j = *it;
+    if (j->state == JS::Staging) { ++it; continue; }
+    j->eout.release();
+    j->esum.release();
+    j->job.reset();
+    reserved -= j->footprint;
+    it = resident.erase(it);
+  }
+  for (auto &kv : jobs) {
+    SJob *j = kv.second.get();
+    if (j->state != JS::Done && j->state != JS::Staging) finish_job(j, s, msg);
+  }
+  cv_done.notify_all();
 }
 
 void ServerImpl::start() {
@@ -581,8 +615,8 @@ te_status te_submit(te_server srv, const te_problem *prob, te_precision prec, ui
   }
   {
     std::lock_guard<std::mutex> lk(S.mu);
-    if (S.stop) return set_error(TE_EBUSY, "server is shutting down");
     if (!S.fatal.empty()) return set_error(TE_EDEVICE, S.fatal);
+    if (S.stop) return set_error(TE_EBUSY, "server is shutting down");
     if ((int)S.queue.size() >= S.max_queued) return set_error(TE_EBUSY, "queue is full");
   }
   std::unique_ptr<SJob> j(new SJob());
