@@ -1,15 +1,19 @@
 """Throughput of the (T) correction on one MI355X.
 
-One step is one whole (T) job on the synthetic o=40, v=400, naux=1200
-workload with the inputs already in HBM: staging from the factors
-(integral assembly, padded layouts, precision copies), the W build over every
-occupied triple, the fused V/D/energy consumer and the reductions, ending
-with E(T) on the host. FP64 is the headline and runs the whole job. FP32 and
-the split-BF16 modes run the same step over a fixed leading slice of the
-triple list (--secondary-frac, default 10%) and report |dE(T)| against the
-FP64 partials of the same triples.
+The workload is one whole FP64 (T) job on the synthetic o=40, v=400,
+naux=1200 problem with the inputs already in HBM: staging from the factors
+(integral assembly, padded layouts), the W build over all 11,440 occupied
+triples, the fused V/D/energy consumer and the reductions. The job is timed
+as --steps steps (default 20): step 0 also stages the job (te_init), step s
+evaluates the s-th contiguous piece of the i-major triple list, and the last
+step also frees the job, so the steps together are exactly one job. Warmup
+steps run the first pieces on a job of their own. FP32 and the split 16-bit
+modes then run a fixed leading piece of the list (--secondary-frac, default
+10%) and report |dE(T)| against the FP64 partials of the same triples.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precisions fp64,fp32,...]
+    python bench.py --workload huge      # o=100 v=800, (vv|vo) on the fly, subset
+    python bench.py --workload serving   # mixed-size jobs, packed server vs sequential
 """
 from __future__ import annotations
 
@@ -59,23 +63,52 @@ def measured_traffic(kernel: str, workload: str):
     return None
 
 
-def cpu_baseline(P, triples):
-    """The CPU oracle as it stands, on a bounded sample of the same workload."""
-    import oracle
+def cpu_info():
+    """CPU model and the number of logical CPUs this process may run on."""
+    model = "unknown"
     try:
-        from threadpoolctl import threadpool_info
-        cores = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
-    except Exception:
-        cores = os.cpu_count() or 1
-    ints = oracle.DFIntegrals(P.B_oo, P.B_ov, P.B_vv, max_cached=6)
-    t0 = time.perf_counter()
-    E, parts = oracle.energy(P.eps_occ, P.eps_vir, P.t1, P.t2, ints, triple_subset=triples)
-    dt = time.perf_counter() - t0
-    fl = len(triples) * 12.0 * P.v ** 3 * (P.v + P.o)
-    return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{len(triples)} occupied triples {', '.join(str(tuple(t)) for t in triples)} "
-                      f"of o={P.o} v={P.v} naux={P.naux}, including their (vv|vo) slice assembly "
-                      f"from the factors; {dt:.1f} s"}, {tuple(p[:3]): p[3] for p in parts}
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, n
+
+
+def cpu_baseline(P, triples, single):
+    """The CPU oracle as it stands, on a bounded sample of the same workload:
+    `triples` on the BLAS thread pool (every core it uses), and `single`
+    (one triple) on one thread. Both include the (vv|vo) slice assembly
+    from the factors that their triples need."""
+    import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
+    model, ncpu = cpu_info()
+    threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
+    fpt = 12.0 * P.v ** 3 * (P.v + P.o)
+
+    def run(sample):
+        ints = oracle.DFIntegrals(P.B_oo, P.B_ov, P.B_vv, max_cached=6)
+        t0 = time.perf_counter()
+        E, parts = oracle.energy(P.eps_occ, P.eps_vir, P.t1, P.t2, ints, triple_subset=sample)
+        return time.perf_counter() - t0, parts
+    dt, parts = run(triples)
+    with threadpool_limits(limits=1):
+        dt1, parts1 = run(single)
+    desc = lambda ts: ", ".join(str(tuple(int(x) for x in t)) for t in ts)  # noqa: E731
+    return {"value": len(triples) * fpt / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{len(triples)} occupied triples {desc(triples)} of o={P.o} v={P.v} "
+                      f"naux={P.naux} in {dt:.1f} s on {threads} BLAS threads, including their "
+                      f"(vv|vo) slice assembly from the factors; numpy FP64",
+            "cpu_model": model, "nproc": ncpu,
+            "single_thread_value": fpt * len(single) / dt1 / 1e12,
+            "single_thread_sample": f"{desc(single)} in {dt1:.1f} s on one thread, with its "
+                                    f"slice assembly"}, {tuple(p[:3]): p[3] for p in parts + parts1}
 
 
 def bench_huge(args) -> int:
@@ -243,8 +276,8 @@ def bench_serving(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16x2,fp16x2")
     ap.add_argument("--o", type=int, default=40)
     ap.add_argument("--v", type=int, default=400)
@@ -253,9 +286,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--secondary-frac", type=float, default=0.1,
                     help="fraction of the triple list (leading slice) the non-FP64 precisions time")
-    ap.add_argument("--cpu-triples", type=int, default=4)
+    ap.add_argument("--cpu-triples", type=int, default=3)
     ap.add_argument("--max-triples", type=int, default=0,
-                    help="exploration only: evaluate the first N triples per step")
+                    help="exploration only: a job of the first N triples")
     ap.add_argument("--workload", choices=("large", "huge", "serving"), default="large")
     ap.add_argument("--sample", type=int, default=2000, help="huge: triples timed")
     ap.add_argument("--cache", type=int, default=0, help="huge: slice cache size (0: auto)")
@@ -282,6 +315,25 @@ def main() -> int:
     if args.workload == "serving":
         return bench_serving(args)
 
+    return bench_large(args)
+
+
+def step_slices(n_triples: int, steps: int):
+    """Contiguous pieces [start, stop) of the i-major triple list, one per
+    step: together the steps evaluate every triple exactly once."""
+    if steps < 1:
+        raise ValueError("need at least one step")
+    edges = np.linspace(0, n_triples, steps + 1).round().astype(np.int64)
+    return [(int(edges[s]), int(edges[s + 1])) for s in range(steps)]
+
+
+def bench_large(args) -> int:
+    """One whole FP64 (T) job at o=40, v=400, naux=1200, timed as `steps`
+    steps: step 0 stages the job (te_init), step s evaluates the s-th
+    contiguous piece of the triple list, and the last step also frees the
+    job. The value is the job's algorithmic flops over the total."""
+    import math
+
     import torch
     from paper_2512_01055_amd import te
     from paper_2512_01055_amd.inputs import make_problem
@@ -299,118 +351,123 @@ def main() -> int:
     P = make_problem(o, v, naux, seed)
     log(f"inputs o={o} v={v} naux={naux} seed={seed} drawn in {time.time() - t0:.1f} s")
     dev = torch.device("cuda:0")
-    names = ("eps_occ", "eps_vir", "t1", "t2", "B_oo", "B_ov", "B_vv")
     D = type("DevProblem", (), {})()
-    for n in names:
+    for n in ("eps_occ", "eps_vir", "t1", "t2", "B_oo", "B_ov", "B_vv"):
         setattr(D, n, torch.from_numpy(getattr(P, n)).to(dev))
     D.o, D.v, D.naux = o, v, naux
     torch.cuda.synchronize()
-    n_tr = int(te.lib().te_num_triples(o))
-    subset = None
-    if args.max_triples and args.max_triples < n_tr:
-        subset = te.triple_list(o)[:args.max_triples]
-        n_tr = len(subset)
-    fl_job = n_tr * te.flops_per_triple(o, v)
+    tl = te.triple_list(o)
+    if args.max_triples:
+        tl = tl[:args.max_triples]
+    n_tr = len(tl)
+    fpt = te.flops_per_triple(o, v)
+    fl_job = n_tr * fpt
+    pieces = step_slices(n_tr, args.steps)
     stream = torch.cuda.current_stream()
 
-    results = {}
-    precs = args.precisions.split(",")
-    head = "fp64" if "fp64" in precs else precs[0]
-    # secondary precisions time a fixed leading slice of the triple list
-    n_sec = n_tr if args.secondary_frac >= 1.0 else max(1, int(round(n_tr * args.secondary_frac)))
-    sec_subset = (subset if subset is not None else te.triple_list(o))[:n_sec]
-    head_pt = None
-    for prec in precs:
-        is_head = prec == head
-        n_this = n_tr if is_head else n_sec
-        fl_this = n_this * te.flops_per_triple(o, v)
-
-        def step():
-            nonlocal head_pt
-            job = te.Job(D, device=0, stream=stream)
-            if is_head and subset is None:
-                E, st, pt = job.energy(prec, per_triple=True)
-            elif is_head:
-                E, pt, st = job.energy_triples(subset, prec)
-            else:
-                E, pt, st = job.energy_triples(sec_subset, prec)
-            job.free()
-            if is_head:
-                head_pt = pt
-            return E, st
+    # warmup: a job of its own, evaluating the first pieces
+    if args.warmup:
+        job = te.Job(D, device=0, stream=stream)
         for w in range(args.warmup):
-            log(f"[{prec}] warmup {w + 1}/{args.warmup}")
-            step()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        sts = []
-        E = None
-        for s in range(args.steps):
-            E, st = step()
-            sts.append(st)
-            log(f"[{prec}] step {s + 1}/{args.steps}: E(T) = {E:.12e} Eh, "
-                f"{st['tflops']:.2f} TFLOP/s in te_energy, W kernel "
-                f"{st['w_kernel_seconds']:.2f} s over {st['w_launches']} launches")
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        wsec = sum(s_["w_kernel_seconds"] for s_ in sts)
-        wl = sum(s_["w_launches"] for s_ in sts)
-        results[prec] = {
-            "E": E, "triples": n_this, "seconds": dt, "ms_per_step": dt / args.steps * 1e3,
-            "tflops": fl_this * args.steps / dt / 1e12,
-            "w_kernel_avg_ms": wsec / max(wl, 1) * 1e3,
-            "w_flops_per_launch": fl_this * args.steps / max(wl, 1),
-            "e_kernel_seconds": sum(s_["e_kernel_seconds"] for s_ in sts),
-            "energy_seconds": sum(s_["seconds"] for s_ in sts),
-        }
+            a, b = pieces[w % len(pieces)]
+            job.energy_triples(tl[a:b], "fp64")
+            log(f"[fp64] warmup {w + 1}/{args.warmup}: triples {a}..{b - 1}")
+        job.free()
+    torch.cuda.synchronize()
 
-    r = results[head]
-    achieved = r["w_flops_per_launch"] / (r["w_kernel_avg_ms"] * 1e-3) / 1e12
+    # timed: te_init, every piece in order, te_free
+    pts, sts, step_s = [], [], []
+    t_start = time.perf_counter()
+    job = te.Job(D, device=0, stream=stream)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t_start
+    for s, (a, b) in enumerate(pieces):
+        ts = time.perf_counter()
+        _, pt, st = job.energy_triples(tl[a:b], "fp64")
+        if s == len(pieces) - 1:
+            job.free()
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - ts + (t_init if s == 0 else 0.0))
+        pts.append(pt)
+        sts.append(st)
+        log(f"[fp64] step {s + 1}/{len(pieces)}: triples {a}..{b - 1} in {step_s[-1]:.3f} s, "
+            f"W kernel {st['w_kernel_seconds']:.3f} s over {st['w_launches']} launches")
+    total = time.perf_counter() - t_start
+    pt64 = np.concatenate(pts)
+    E64 = math.fsum(pt64.tolist())
+    wsec = sum(x["w_kernel_seconds"] for x in sts)
+    wl = sum(x["w_launches"] for x in sts)
+    w_flops_per_launch = fl_job / max(wl, 1)
+    achieved = w_flops_per_launch / (wsec / max(wl, 1)) / 1e12
+    log(f"[fp64] job: E(T) = {E64:.12e} Eh in {total:.2f} s (te_init {t_init:.3f} s), "
+        f"{fl_job / total / 1e12:.2f} TFLOP/s; W kernel {achieved:.2f} TFLOP/s")
+
+    precs_out = {"fp64": {"tflops": round(fl_job / total / 1e12, 4), "triples": n_tr, "E": E64,
+                          "seconds": round(total, 3), "init_seconds": round(t_init, 4),
+                          "w_kernel_tflops": round(achieved, 3),
+                          "w_kernel_avg_ms": round(wsec / max(wl, 1) * 1e3, 4),
+                          "e_kernel_seconds": round(sum(x["e_kernel_seconds"] for x in sts), 3),
+                          "issued_mfma_tflops": round(achieved, 3), "peak": PEAK_TFLOPS["fp64"]}}
+
+    # the other precisions on a fixed leading piece of the same list, on a
+    # job of their own; |dE| against the FP64 partials of the same triples
+    n_sec = max(1, int(round(n_tr * args.secondary_frac)))
+    sec = [p_ for p_ in args.precisions.split(",") if p_ != "fp64"]
+    if sec:
+        job = te.Job(D, device=0, stream=stream)
+        for prec in sec:
+            ts = time.perf_counter()
+            E, pt, st = job.energy_triples(tl[:n_sec], prec)
+            dt = time.perf_counter() - ts
+            Eref = math.fsum(pt64[:n_sec].tolist())
+            Es = math.fsum(pt.tolist())
+            wr = n_sec * fpt / st["w_kernel_seconds"] / 1e12
+            precs_out[prec] = {
+                "tflops": round(n_sec * fpt / dt / 1e12, 4), "triples": n_sec, "E": Es,
+                "seconds": round(dt, 3), "setup_seconds": round(st["stage_seconds"], 3),
+                "w_kernel_tflops": round(wr, 3), "issued_mfma_tflops": round(ISSUED[prec] * wr, 3),
+                "peak": PEAK_TFLOPS[prec], "E_fp64_same_triples": Eref,
+                "dE_vs_fp64": abs(Es - Eref), "dE_rel": abs(Es - Eref) / abs(Eref)}
+            log(f"[{prec}] {n_sec} triples in {dt:.2f} s (operand conversion "
+                f"{st['stage_seconds']:.2f} s): W kernel {wr:.1f} TFLOP/s, "
+                f"|dE| vs FP64 {abs(Es - Eref):.3e} Eh ({abs(Es - Eref) / abs(Eref):.2e} rel)")
+        job.free()
+    del D
+    torch.cuda.empty_cache()
+
     out = {
-        "metric": METRIC, "value": round(r["tflops"], 4), "unit": "TFLOP/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(r["ms_per_step"], 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x2": "bf16x2",
-                  "fp16x2": "fp16x2"}[head],
-        "data": "synthetic",
+        "metric": METRIC, "value": round(fl_job / total / 1e12, 4), "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": len(pieces), "warmup": args.warmup,
+        "ms_per_step": round(total / len(pieces) * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"(T) of closed-shell CCSD(T), o={o} v={v} naux={naux}, "
-                               f"seeded synthetic DF factors and MP2-like amplitudes (seed {seed}), "
-                               f"{n_tr} occupied triples, {fl_job:.4e} algorithmic flop per job",
-                   "precision": head},
+                               f"seeded synthetic DF factors and MP2-like amplitudes (seed {seed}); "
+                               f"one whole job ({n_tr} occupied triples, {fl_job:.4e} algorithmic "
+                               f"flop) split into {len(pieces)} steps of consecutive triples, "
+                               f"te_init in the first step",
+                   "precision": "fp64"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
-                     "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_TFLOPS[head], 4),
-                     "traffic": measured_traffic(f"wbuild_kernel<{head}>", f"o{o}_v{v}"),
+                     "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_TFLOPS["fp64"], 4),
+                     "traffic": measured_traffic("wbuild_kernel<fp64>", f"o{o}_v{v}"),
                      "traffic_unit": "bytes/launch",
-                     "kernel": f"wbuild_kernel<{head}>",
-                     "avg_launch_ms": round(r["w_kernel_avg_ms"], 4),
-                     "sustained_mfma_tflops": round(te.mfma_sustained(head if head in ("fp64", "fp32", "bf16x3") else "bf16x3", 2.0), 2)},
+                     "kernel": "wbuild_kernel<fp64>",
+                     "launches": int(wl), "w_flops_per_launch": w_flops_per_launch,
+                     "avg_launch_ms": round(wsec / max(wl, 1) * 1e3, 4)},
+        "step_seconds": [round(x, 4) for x in step_s],
+        "precisions": precs_out,
     }
-    precs_out = {}
-    for p_, rr in results.items():
-        d = {"tflops": round(rr["tflops"], 4), "ms_per_step": round(rr["ms_per_step"], 3),
-             "triples": rr["triples"], "E": rr["E"],
-             "w_kernel_tflops": round(rr["w_flops_per_launch"] / (rr["w_kernel_avg_ms"] * 1e-3) / 1e12, 3),
-             "issued_mfma_tflops": round(ISSUED[p_] * rr["w_flops_per_launch"]
-                                         / (rr["w_kernel_avg_ms"] * 1e-3) / 1e12, 3),
-             "peak": PEAK_TFLOPS[p_]}
-        if p_ != head and head == "fp64" and head_pt is not None:
-            # same triples in FP64, summed in list order from the FP64 run
-            E64 = float(np.sum(head_pt[:rr["triples"]]))
-            dE = abs(rr["E"] - E64)
-            d["E_fp64_same_triples"] = E64
-            d["dE_vs_fp64"] = dE
-            d["dE_rel"] = dE / abs(E64)
-        precs_out[p_] = d
-    out["precisions"] = precs_out
     if not args.no_cpu:
-        from paper_2512_01055_amd.inputs import triple_list
-        tl = triple_list(o)
+        # all cores on three triples (three slices assembled), one thread on one
         sample = [tuple(int(x) for x in t) for t in tl[1:1 + args.cpu_triples]]
-        log(f"cpu baseline: oracle on {sample}")
-        cb, _ = cpu_baseline(P, sample)
+        single = [tuple(int(x) for x in tl[0])]
+        log(f"cpu baseline: oracle on {sample} (all cores) and {single} (one thread)")
+        cb, ref = cpu_baseline(P, sample, single)
         out["cpu_baseline"] = cb
+        # the oracle's values of those triples against the device's
+        pos = {tuple(int(x) for x in t): q for q, t in enumerate(tl)}
+        out["cpu_baseline"]["max_rel_diff_vs_device"] = max(
+            abs(pt64[pos[k]] - e) / abs(e) for k, e in ref.items())
     print(json.dumps(out), flush=True)
     return 0
 
