@@ -171,6 +171,29 @@ te_status te_energy(te_job job, te_precision prec, double *e_t, double *per_trip
 te_status te_energy_triples(te_job job, te_precision prec, const int32_t *ijk, int64_t n,
                             double *e_sum, double *per_triple, te_stats *st);
 
+/* te_energy_triples for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same arguments, results bitwise those of te_energy_triples
+ * (same kernels, same launch items); st gets seconds, flops, tflops and
+ * n_triples only. Allocates no device memory: the launch items, the W shares
+ * of the batches in flight, the sextet partials and the per-triple results
+ * live in one static device array of 512 MiB (one per device the call runs
+ * on, held until the process ends). Needs a job staged by te_init with
+ * resident (vv|vo) slices and t2 in device memory, and, for a reduced
+ * precision, the operand copy an earlier te_energy / te_energy_triples call
+ * in that precision made (TE_EINVAL otherwise). A list whose launch items
+ * and per-triple results together with one triple's W shares (3 v^3 values
+ * of 8 bytes in FP64, 4 otherwise, v rounded up to 8) exceed the array is
+ * rejected with TE_EINVAL: in FP64 one triple's W fits for v up to 280, two
+ * triples in flight (W build overlapping the energy) for v up to 216; FP32
+ * and the split 16-bit modes (W in FP32) reach 352 and 280. The
+ * array's contents persist between calls and are overwritten by each; calls
+ * on one device are serialised inside the library (one process holds one
+ * array per device, and two processes never share one). */
+te_status te_energy_triples_noalloc(te_job job, te_precision prec, const int32_t *ijk,
+                                    int64_t n, double *e_sum, double *per_triple,
+                                    te_stats *st);
+
 /* E(T) split by perturbation order into the two parts that make up the (T)
  * correction (its fourth- and fifth-order connected-triples terms, as the
  * introduction of the paper describes them): E[4] collects the W Z / D

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libte.so")
-SOURCES = ["te_wbuild.hip", "te_kernels.hip", "te_api.cpp", "te_server.cpp", "te_checkpoint.cpp"]
+SOURCES = ["te_wbuild.hip", "te_kernels.hip", "te_api.cpp", "te_server.cpp", "te_checkpoint.cpp",
+           "te_noalloc.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

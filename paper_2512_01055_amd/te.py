@@ -61,7 +61,8 @@ class ServerConfig(C.Structure):
 
 _lib: Optional[C.CDLL] = None
 
-EXPORTS = ["te_init", "te_energy", "te_energy_triples", "te_energy_terms",
+EXPORTS = ["te_init", "te_energy", "te_energy_triples", "te_energy_triples_noalloc",
+           "te_energy_terms",
            "te_energy_checkpointed", "te_checkpoint_scan", "te_free", "te_num_triples",
            "te_triple_list", "te_flops_per_triple", "te_plan_slice_loads", "te_server_create", "te_submit",
            "te_poll", "te_wait", "te_server_destroy", "te_strerror", "te_last_error"]
@@ -88,6 +89,7 @@ def lib() -> C.CDLL:
     L.te_energy.argtypes = [P, S, C.POINTER(C.c_double), C.c_void_p, C.POINTER(Stats)]
     L.te_energy_triples.argtypes = [P, S, C.c_void_p, C.c_int64, C.POINTER(C.c_double),
                                     C.c_void_p, C.POINTER(Stats)]
+    L.te_energy_triples_noalloc.argtypes = L.te_energy_triples.argtypes
     D = C.POINTER(C.c_double)
     L.te_energy_terms.argtypes = [P, S, C.c_void_p, C.c_int64, D, D, C.c_void_p, C.c_void_p,
                                   C.POINTER(Stats)]
@@ -114,7 +116,8 @@ def lib() -> C.CDLL:
     L.te_strerror.argtypes = [S]
     L.te_strerror.restype = C.c_char_p
     L.te_last_error.restype = C.c_char_p
-    for f in ("te_init", "te_energy", "te_energy_triples", "te_energy_terms",
+    for f in ("te_init", "te_energy", "te_energy_triples", "te_energy_triples_noalloc",
+              "te_energy_terms",
               "te_energy_checkpointed", "te_checkpoint_scan", "te_free", "te_triple_list",
               "te_server_create", "te_submit", "te_poll", "te_wait", "te_server_destroy"):
         getattr(L, f).restype = S
@@ -226,6 +229,18 @@ class Job:
         pt = np.zeros(len(t))
         _check(L.te_energy_triples(self._h, PRECISIONS[precision], t.ctypes.data, len(t),
                                    C.byref(e), pt.ctypes.data, C.byref(st)))
+        return e.value, pt, st.as_dict()
+
+    def energy_triples_noalloc(self, ijk: Sequence, precision: str = "fp64"):
+        """energy_triples through the entry point that allocates no device
+        memory (its scratch is a static device array); same returns."""
+        L = lib()
+        t = np.ascontiguousarray(np.asarray(ijk, dtype=np.int32).reshape(-1, 3))
+        e = C.c_double()
+        st = Stats()
+        pt = np.zeros(len(t))
+        _check(L.te_energy_triples_noalloc(self._h, PRECISIONS[precision], t.ctypes.data,
+                                           len(t), C.byref(e), pt.ctypes.data, C.byref(st)))
         return e.value, pt, st.as_dict()
 
     def energy_terms(self, precision: str = "fp64", triples: Optional[Sequence] = None):
