@@ -111,6 +111,13 @@ template <typename T> struct Chunk {
 #pragma unroll
     for (int i = 0; i < NQ; ++i) q[i] = s[i];
   }
+  // from a base shared by the wave plus a per-lane 32-bit byte offset (lets
+  // the compiler use a scalar base register and no 64-bit address add)
+  __device__ void load_at(const T *base, uint32_t byte_off) {
+    gptr<u32x4> s = (gptr<u32x4>)(reinterpret_cast<const char *>(base) + byte_off);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) q[i] = s[i];
+  }
 };
 
 __device__ inline d4 mma(double a, double b, d4 c) {

@@ -54,6 +54,12 @@ __device__ inline Setup make_setup(int g, int i, int j, int k) {
   return s;
 }
 
+// Sixteen zero bytes in global memory: the source of LDS chunks that lie past
+// the end of K (the LDS-DMA loads below write whatever their source holds).
+__device__ __attribute__((aligned(16))) const unsigned int kZero16[4] = {0u, 0u, 0u, 0u};
+
+typedef __attribute__((address_space(3))) void *lds_ptr;
+
 // NB: 16-column blocks per tile (BN = 16 NB); WM: 16-row blocks per wave
 // (BM = 4 waves x 16 WM rows). The register budget asks for three waves per
 // SIMD. The two LDS stages hold 2 NP (BM + BN) KT elements: 52 KiB at
@@ -70,12 +76,13 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
   constexpr int KT = TR::KT, LD = TR::KT + TR::PAD, NP = TR::NP, KM = TR::KM;
   constexpr int BN = 16 * NB;
   constexpr int BM = 64 * WM;
-  constexpr int CPR = KT / 8;                     // 8-element chunks per row
-  constexpr int CA = (BM * KT / 8 + WG - 1) / WG; // A chunks per thread
-  constexpr int CB = (BN * KT / 8 + WG - 1) / WG; // B chunks per thread
 
-  __shared__ __attribute__((aligned(16))) T As[2][NP][BM][LD];
-  __shared__ __attribute__((aligned(16))) T Bs[2][NP][BN][LD];
+  // two LDS stages as separate objects, so that the compiler can tell the
+  // stage being filled by LDS-DMA loads from the one being read
+  __shared__ __attribute__((aligned(16))) T As0[NP][BM][LD], As1[NP][BM][LD];
+  __shared__ __attribute__((aligned(16))) T Bs0[NP * BN][LD], Bs1[NP * BN][LD];
+  using AT = T (*)[BM][LD];
+  using BT = T (*)[LD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -112,195 +119,223 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
   // the occupied segments' t2[op][l] (row panel) or t2[l][op] (column panel)
   const T *TB0 = reinterpret_cast<const T *>(w.Tc[su.tr[0]]) + (long)su.tq[0] * w.tcs;
   const T *TB1 = reinterpret_cast<const T *>(w.Tc[su.tr[1]]) + (long)su.tq[1] * w.tcs;
-
-  // --- per-thread row pointers for the X phase
-  long rowA[CA][2];
-  int  kcA[CA];
-  bool okA[CA];
-#pragma unroll
-  for (int u = 0; u < CA; ++u) {
-    int c = tid + u * WG;
-    int row = c / CPR;
-    kcA[u] = (c % CPR) * 8;
-    long m = m0 + row;
-    okA[u] = (c < BM * CPR) && (m < M);
-    long mm = okA[u] ? m : 0;
-    long mx = mm / vp, my = mm - mx * vp;
-    rowA[u][0] = mm * vp;
-    rowA[u][1] = (my * vp + mx) * vp;
-  }
-  long rowB[CB];
-  long rowI[CB][2];
-  int kcB[CB];
-  bool okB[CB];
-#pragma unroll
-  for (int u = 0; u < CB; ++u) {
-    int c = tid + u * WG;
-    int row = c / CPR;
-    kcB[u] = (c % CPR) * 8;
-    int n = n0 + row;
-    okB[u] = (c < BN * CPR) && (n < vp);
-    long nn = okB[u] ? n : 0;
-    rowB[u] = nn * vp;
-  }
   const T *TO[2];
   long ksO[2];
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    if (su.om[s] == 0) { TO[s] = reinterpret_cast<const T *>(w.Tr[su.op[s]]); ksO[s] = (long)w.trs; }
-    else               { TO[s] = reinterpret_cast<const T *>(w.Tc[su.op[s]]); ksO[s] = (long)w.tcs; }
+  for (int q = 0; q < 2; ++q) {
+    if (su.om[q] == 0) { TO[q] = reinterpret_cast<const T *>(w.Tr[su.op[q]]); ksO[q] = (long)w.trs; }
+    else               { TO[q] = reinterpret_cast<const T *>(w.Tc[su.op[q]]); ksO[q] = (long)w.tcs; }
   }
-  // 16-bit modes: occupied-segment rows of T2T (t_{p l}^{yz} with l last), read
-  // like the X rows; om = 1 takes the swapped pair (t_{l p}^{yz} = t_{p l}^{zy})
-  const int lo = w.lo;
+  // 16-bit modes: occupied-segment rows of the row form (t_{p l}^{yz} with l
+  // last, rows of lo); om = 1 takes the swapped pair (t_{l p}^{yz} = t_{p l}^{zy})
   const T *TT0 = reinterpret_cast<const T *>(w.Tt[su.op[0]]);
   const T *TT1 = reinterpret_cast<const T *>(w.Tt[su.op[1]]);
-  long rowO[TR::SPLIT ? CA : 1][2];
-  if constexpr (TR::SPLIT) {
-#pragma unroll
-    for (int u = 0; u < CA; ++u) {
-      long mm = okA[u] ? (long)m0 + (tid + u * WG) / CPR : 0;
-      long mx = mm / vp, my = mm - mx * vp;
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-        rowO[u][s] = (su.om[s] ? my * vp + mx : mm) * lo;
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < CB; ++u) {   // In rows have length lo
-    long nn = okB[u] ? (long)n0 + (tid + u * WG) / CPR : 0;
-    rowI[u][0] = (((long)su.ix[0] * vp + nn) * o + su.iy[0]) * lo;
-    rowI[u][1] = (((long)su.ix[1] * vp + nn) * o + su.iy[1]) * lo;
-  }
 
+  const int lo = w.lo;
   const int KX = 2 * vp;
   const int KO = TR::SPLIT ? 2 * lo : 2 * o;
   const int nkx = (KX + KT - 1) / KT;
   const int nko = (KO + KT - 1) / KT;
   const int ntiles = nkx + nko;
+  constexpr size_t ES = sizeof(T);
 
-  Chunk<T> ra[CA][NP], rb[CB][NP];
+  // ---- LDS-DMA loads: the X phase in every precision, and the occupied
+  // phase of the 16-bit modes (whose operands are K-contiguous rows too).
+  // Wave-load g of a region writes its 16-byte LDS chunks [64 g, 64 g + 64):
+  // lane L writes chunk q = 64 g + L, i.e. row q / CR, slot q % CR of the
+  // region's part, and so loads the global chunk the swizzle keeps in that
+  // slot (slot ^ ((row / RP) % CR)). Rows past the matrix are clamped to row
+  // 0 (their products land in rows or columns the epilogue never stores);
+  // chunks past the end of K are read from kZero16.
+  using SW = Swz<TR>;
+  constexpr int EC = SW::EC, CRW = SW::CR, RPW = SW::RP;
+  constexpr int GPA = BM * CRW / 64;         // A wave-loads per part
+  constexpr int IAP = GPA / 4;               // ... per part and wave
+  constexpr int GPB = BN * CRW / 64;         // B wave-loads per part
+  constexpr int IB = (NP * GPB + 3) / 4;     // B wave-loads per wave; spare ones
+                                             // repeat an earlier block (same bytes)
+  static_assert(GPA % 4 == 0, "A tile must split evenly over four waves");
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  uintptr_t pA0[IAP], pA1[IAP];                          // X segment 0 / 1 (minus vp)
+  uintptr_t pO0[TR::SPLIT ? IAP : 1], pO1[TR::SPLIT ? IAP : 1];  // row form (minus lo)
+  int cA[IAP];                                           // k offset of the chunk
+#pragma unroll
+  for (int jj = 0; jj < IAP; ++jj) {
+    const int q = 64 * (wv * IAP + jj) + lane;
+    const int r = q / CRW;
+    const int c = (q % CRW) ^ ((r / RPW) % CRW);
+    const long m = (long)m0 + r;
+    const long mm = m < M ? m : 0;
+    const long mx = mm / vp, my = mm - mx * vp;
+    cA[jj] = c * EC;
+    pA0[jj] = reinterpret_cast<uintptr_t>(XA0) + (uintptr_t)((mm * vp + c * EC) * (long)ES);
+    pA1[jj] = reinterpret_cast<uintptr_t>(XA1) + (uintptr_t)(((my * vp + mx) * vp + c * EC - vp) * (long)ES);
+    if constexpr (TR::SPLIT) {
+      pO0[jj] = reinterpret_cast<uintptr_t>(TT0) +
+                (uintptr_t)(((su.om[0] ? my * vp + mx : mm) * lo + c * EC) * (long)ES);
+      pO1[jj] = reinterpret_cast<uintptr_t>(TT1) +
+                (uintptr_t)(((su.om[1] ? my * vp + mx : mm) * lo + c * EC - lo) * (long)ES);
+    }
+  }
+  int oB[IB], oI0[IB], oI1[IB];        // element offsets of the lane's B chunk
+                                       // (oI1 is relative to k = lo: may be < 0)
+  int cB[IB], gB[IB], prB[IB];         // k offset; LDS block and part (uniform)
+#pragma unroll
+  for (int j = 0; j < IB; ++j) {
+    const int g2 = (j * 4 + wv) % (NP * GPB);
+    gB[j] = g2;
+    prB[j] = g2 / GPB;
+    const int q = 64 * (g2 % GPB) + lane;
+    const int r = q / CRW;
+    const int c = (q % CRW) ^ ((r / RPW) % CRW);
+    const int n = n0 + r;
+    const long nn = n < vp ? n : 0;
+    cB[j] = c * EC;
+    oB[j] = (int)(nn * vp + c * EC);
+    oI0[j] = (int)((((long)su.ix[0] * vp + nn) * o + su.iy[0]) * lo + c * EC);
+    oI1[j] = (int)((((long)su.ix[1] * vp + nn) * o + su.iy[1]) * lo + c * EC - lo);
+  }
 
-  auto load = [&](int t) {
+  auto dma = [](uintptr_t src, char *dst) __attribute__((always_inline)) {
+    __builtin_amdgcn_global_load_lds((gptr<u32x4>)src, (lds_ptr)dst, 16, 0, 0);
+  };
+  const uintptr_t zero = reinterpret_cast<uintptr_t>(kZero16);
+
+  auto issue = [&](int t, AT As, BT Bs) __attribute__((always_inline)) {
+    char *sA = reinterpret_cast<char *>(&As[0][0][0]);
+    char *sB = reinterpret_cast<char *>(&Bs[0][0]);
     if (t < nkx) {
       const int kb = t * KT;
+      if (kb + KT <= vp || (kb >= vp && kb + KT <= KX)) {
+        // the whole tile lies in one segment
+        const bool s1 = kb >= vp;
+        const T *tb = (s1 ? TB1 : TB0) + (kb - (s1 ? vp : 0));
 #pragma unroll
-      for (int u = 0; u < CA; ++u) {
-        int kg = kb + kcA[u];
-        bool ok = okA[u] && kg < KX;
-        int seg = kg >= vp;
-        long off = rowA[u][seg] + (kg - seg * vp);
-        const T *xb = seg ? XA1 : XA0;
+        for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          if (ok) ra[u][p].load(xb + p * w.xps + off); else ra[u][p].zero();
-        }
-      }
+          for (int jj = 0; jj < IAP; ++jj)
+            dma((s1 ? pA1[jj] : pA0[jj]) + (uintptr_t)(((long)kb + p * (long)w.xps) * (long)ES),
+                sA + (p * GPA + wv * IAP + jj) * 1024);
 #pragma unroll
-      for (int u = 0; u < CB; ++u) {
-        int kg = kb + kcB[u];
-        bool ok = okB[u] && kg < KX;
-        int seg = kg >= vp;
-        long off = rowB[u] + (kg - seg * vp);
-        const T *tb = seg ? TB1 : TB0;
+        for (int j = 0; j < IB; ++j)
+          dma(reinterpret_cast<uintptr_t>(tb + prB[j] * w.tcps + oB[j]), sB + gB[j] * 1024);
+      } else {
+        // the tile that straddles k = vp, or a ragged last one
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          if (ok) rb[u][p].load(tb + p * w.tcps + off); else rb[u][p].zero();
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int jj = 0; jj < IAP; ++jj) {
+            const int k = kb + cA[jj];
+            const uintptr_t src = (k >= vp ? pA1[jj] : pA0[jj]) +
+                                  (uintptr_t)(((long)kb + p * (long)w.xps) * (long)ES);
+            dma(k >= KX ? zero : src, sA + (p * GPA + wv * IAP + jj) * 1024);
+          }
+#pragma unroll
+        for (int j = 0; j < IB; ++j) {
+          const int k = kb + cB[j];
+          const bool s1 = k >= vp;
+          const T *tb = (s1 ? TB1 : TB0) + prB[j] * w.tcps + oB[j] + (kb - (s1 ? vp : 0));
+          dma(k >= KX ? zero : reinterpret_cast<uintptr_t>(tb), sB + gB[j] * 1024);
         }
       }
     } else if constexpr (TR::SPLIT) {
-      // occupied segments as 8-element chunks of K-contiguous rows
-      const int kb = (t - nkx) * KT;
+      const int ko = (t - nkx) * KT;
 #pragma unroll
-      for (int u = 0; u < CA; ++u) {
-        int kg = kb + kcA[u];
-        bool ok = okA[u] && kg < KO;
-        int seg = kg >= lo;
-        long off = rowO[u][seg] + (kg - seg * lo);
-        const T *tt = seg ? TT1 : TT0;
+      for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          if (ok) ra[u][p].load(tt + p * w.t2tps + off); else ra[u][p].zero();
+        for (int jj = 0; jj < IAP; ++jj) {
+          const int k = ko + cA[jj];
+          const uintptr_t src = (k >= lo ? pO1[jj] : pO0[jj]) +
+                                (uintptr_t)(((long)ko + p * (long)w.t2tps) * (long)ES);
+          dma(k >= KO ? zero : src, sA + (p * GPA + wv * IAP + jj) * 1024);
         }
-      }
 #pragma unroll
-      for (int u = 0; u < CB; ++u) {
-        int kg = kb + kcB[u];
-        bool ok = okB[u] && kg < KO;
-        int seg = kg >= lo;
-        long off = rowI[u][seg] + (kg - seg * lo);
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          if (ok) rb[u][p].load(In + p * w.ips + off); else rb[u][p].zero();
-        }
-      }
-    } else {
-      // K-major A: thread c takes k = c % KT and eight consecutive m, so the
-      // transposed LDS stores of a lane group fill one row (conflict-free)
-      const int kb = (t - nkx) * KT;
-#pragma unroll
-      for (int u = 0; u < CA; ++u) {
-        int c = tid + u * WG;
-        int kk = c % KT;
-        int mc = (c / KT) * 8;
-        int kg = kb + kk;
-        long m = m0 + mc;
-        bool ok = (c < BM * CPR) && kg < KO && m < M;
-        int seg = kg >= o;
-        long off = (long)(kg - seg * o) * ksO[seg] + m;
-        const T *to = seg ? TO[1] : TO[0];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          if (ok) ra[u][p].load(to + p * w.tcps + off); else ra[u][p].zero();
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < CB; ++u) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          int kg = kb + kcB[u] + e;
-          bool ok = okB[u] && kg < KO;
-          int seg = kg >= o;
-          long off = rowI[u][seg] + (kg - seg * o);
-#pragma unroll
-          for (int p = 0; p < NP; ++p) rb[u][p].set(e, ok ? gld(In + p * w.ips + off) : T(0));
-        }
+      for (int j = 0; j < IB; ++j) {
+        const int k = ko + cB[j];
+        const T *ib = In + prB[j] * w.ips + ko + (k >= lo ? oI1[j] : oI0[j]);
+        dma(k >= KO ? zero : reinterpret_cast<uintptr_t>(ib), sB + gB[j] * 1024);
       }
     }
   };
 
-  auto store = [&](int t, int buf) {
-    if (t < nkx || TR::SPLIT) {
+  // ---- FP64 / FP32 occupied phase: the t2 panels are m-contiguous for a
+  // fixed l, so that tile goes through registers and a transposed LDS store.
+  // Every load is unconditional, from an address inside its array (a
+  // predicated load makes the compiler wait for all loads in flight right
+  // away); chunks or elements past K are zeroed when stored.
+  constexpr int CA = TR::SPLIT ? 1 : (BM * KT / 8 + WG - 1) / WG;   // 8-element chunks
+  constexpr int CB = TR::SPLIT ? 1 : (BN * KT / 8 + WG - 1) / WG;
+  constexpr int CPR = KT / 8;
+  Chunk<T> ra[CA], rb[CB];
+  uint32_t zA[CA], zB[CB];
+  long rowI[CB][2];
+  int kcB[CB];
+#pragma unroll
+  for (int u = 0; u < CB; ++u) {
+    const int c = tid + u * WG;
+    kcB[u] = (c % CPR) * 8;
+    const int n = n0 + c / CPR;
+    const long nn = (c < BN * CPR && n < vp) ? n : 0;
+    rowI[u][0] = (((long)su.ix[0] * vp + nn) * o + su.iy[0]) * lo;
+    rowI[u][1] = (((long)su.ix[1] * vp + nn) * o + su.iy[1]) * lo;
+  }
+
+  auto load = [&](int t) __attribute__((always_inline)) {
+    if constexpr (!TR::SPLIT) {
+      // K-major A: thread c takes k = c % KT and eight consecutive m, so the
+      // transposed LDS stores of a lane group fill one row (conflict-free)
+      const int ko = (t - nkx) * KT;
 #pragma unroll
       for (int u = 0; u < CA; ++u) {
-        int c = tid + u * WG;
-        if (c < BM * CPR) {
-          int row = c / CPR;
-#pragma unroll
-          for (int p = 0; p < NP; ++p) store_chunk<TR>(&As[buf][p][row][0], row, kcA[u], ra[u][p]);
-        }
+        const int c = tid + u * WG;
+        const int kg = ko + c % KT;
+        const long m = m0 + (c / KT) * 8;
+        const bool ok = (c < BM * CPR) && kg < KO && m < M;
+        const int seg = ok && kg >= o;
+        const long off = ok ? (long)(kg - seg * o) * ksO[seg] + m : 0;
+        zA[u] = ok ? 0u : ~0u;
+        ra[u].load(TO[seg] + off);
       }
-    } else {
 #pragma unroll
-      for (int u = 0; u < CA; ++u) {
-        int c = tid + u * WG;
-        if (c < BM * CPR) {
-          int kk = c % KT;
-          int mc = (c / KT) * 8;
+      for (int u = 0; u < CB; ++u) {
+        uint32_t z = 0;
 #pragma unroll
-          for (int p = 0; p < NP; ++p)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) As[buf][p][mc + e][lcol<TR>(mc + e, kk)] = ra[u][p].get(e);
+        for (int e = 0; e < 8; ++e) {
+          const int kg = ko + kcB[u] + e;
+          const bool ok = kg < KO;
+          const int seg = ok && kg >= o;
+          const long off = rowI[u][seg] + (ok ? kg - seg * o : 0);
+          z |= ok ? 0u : 1u << e;
+          rb[u].set(e, gld(In + off));
         }
+        zB[u] = z;
       }
     }
+  };
+
+  auto store = [&](AT As, BT Bs) __attribute__((always_inline)) {
+    if constexpr (!TR::SPLIT) {
 #pragma unroll
-    for (int u = 0; u < CB; ++u) {
-      int c = tid + u * WG;
-      if (c < BN * CPR) {
-        int row = c / CPR;
+      for (int u = 0; u < CA; ++u) {
+        const int c = tid + u * WG;
+        if (zA[u]) ra[u].zero();
+        if (c < BM * CPR) {
+          const int kk = c % KT;
+          const int mc = (c / KT) * 8;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) store_chunk<TR>(&Bs[buf][p][row][0], row, kcB[u], rb[u][p]);
+          for (int e = 0; e < 8; ++e) As[0][mc + e][lcol<TR>(mc + e, kk)] = ra[u].get(e);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        const int c = tid + u * WG;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if ((zB[u] >> e) & 1u) rb[u].set(e, T(0));
+        if (c < BN * CPR) {
+          const int row = c / CPR;
+          store_chunk<TR>(&Bs[row][0], row, kcB[u], rb[u]);
+        }
       }
     }
   };
@@ -317,12 +352,18 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
   const int fr = lane & 15;
   const int fk = lane >> 4;
 
-  load(0);
-  store(0, 0);
-  __syncthreads();
-  for (int t = 0; t < ntiles; ++t) {
-    const int cur = t & 1;
-    if (t + 1 < ntiles) load(t + 1);
+  // Pipeline: two LDS stages; the next tile's loads are in flight while this
+  // one is computed. The barrier is the bare s_barrier after an explicit
+  // wait for this wave's loads and LDS accesses (a __syncthreads fence would
+  // also order the LDS-DMA writes against every later LDS read and make the
+  // compiler wait for the next tile's loads before computing this one).
+  auto sync = [] {
+    __builtin_amdgcn_sched_barrier(0);   // the tile's MFMAs issue before the wait
+    __builtin_amdgcn_s_waitcnt(0);       // vmcnt(0) expcnt(0) lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto compute = [&](AT As, BT Bs) __attribute__((always_inline)) {
 #pragma unroll
     for (int kk = 0; kk < KT / KM; ++kk) {
       if constexpr (NP == 1) {
@@ -331,10 +372,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
 #pragma unroll
         for (int rb_ = 0; rb_ < WM; ++rb_) {
           const int r = wrow + rb_ * 16 + fr;
-          av[rb_] = As[cur][0][r][lcol<TR>(r, kk * 4 + fk)];
+          av[rb_] = As[0][r][lcol<TR>(r, kk * 4 + fk)];
         }
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) bv[cb] = Bs[cur][0][cb * 16 + fr][lcol<TR>(cb * 16 + fr, kk * 4 + fk)];
+        for (int cb = 0; cb < NB; ++cb) bv[cb] = Bs[cb * 16 + fr][lcol<TR>(cb * 16 + fr, kk * 4 + fk)];
 #pragma unroll
         for (int rb_ = 0; rb_ < WM; ++rb_)
 #pragma unroll
@@ -347,12 +388,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
 #pragma unroll
           for (int p = 0; p < NP; ++p)
             av[rb_][p] = *reinterpret_cast<const F *>(
-                &As[cur][p][wrow + rb_ * 16 + fr][lcol<TR>(wrow + rb_ * 16 + fr, fk * 8)]);
+                &As[p][wrow + rb_ * 16 + fr][lcol<TR>(wrow + rb_ * 16 + fr, fk * 8)]);
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
           for (int p = 0; p < NP; ++p)
-            bv[cb][p] = *reinterpret_cast<const F *>(&Bs[cur][p][cb * 16 + fr][lcol<TR>(cb * 16 + fr, fk * 8)]);
+            bv[cb][p] = *reinterpret_cast<const F *>(&Bs[p * BN + cb * 16 + fr][lcol<TR>(cb * 16 + fr, fk * 8)]);
 #pragma unroll
         for (int rb_ = 0; rb_ < WM; ++rb_)
 #pragma unroll
@@ -366,8 +407,46 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
           }
       }
     }
-    if (t + 1 < ntiles) store(t + 1, cur ^ 1);
-    __syncthreads();
+  };
+
+  // LDS-DMA tiles: every tile in the 16-bit modes, the X phase otherwise.
+  // The loop runs two tiles per trip so that each stage is a fixed object;
+  // the loads are issued unconditionally (past the last tile they fetch it
+  // again into the stage no longer read), which keeps the compiler's wait
+  // accounting exact.
+  const int ndma = TR::SPLIT ? ntiles : nkx;
+  auto dma_step = [&](int t, AT Ac, BT Bc, AT An, BT Bn) __attribute__((always_inline)) {
+    issue(t + 1 < ndma ? t + 1 : ndma - 1, An, Bn);
+    compute(Ac, Bc);
+    sync();
+  };
+  issue(0, As0, Bs0);
+  sync();
+  int t = 0;
+  for (; t + 1 < ndma; t += 2) {
+    dma_step(t, As0, Bs0, As1, Bs1);
+    dma_step(t + 1, As1, Bs1, As0, Bs0);
+  }
+  if (t < ndma) {
+    dma_step(t, As0, Bs0, As1, Bs1);
+    ++t;
+  }
+  // FP64 / FP32 occupied phase through registers (stages continue to
+  // alternate; t is the next tile)
+  if constexpr (!TR::SPLIT) {
+    if (t < ntiles) {
+      const bool odd = t & 1;
+      load(t);
+      store(odd ? AT(As1) : AT(As0), odd ? BT(Bs1) : BT(Bs0));
+      sync();
+      for (; t < ntiles; ++t) {
+        const bool cur1 = t & 1;
+        if (t + 1 < ntiles) load(t + 1);
+        compute(cur1 ? AT(As1) : AT(As0), cur1 ? BT(Bs1) : BT(Bs0));
+        if (t + 1 < ntiles) store(cur1 ? AT(As0) : AT(As1), cur1 ? BT(Bs0) : BT(Bs1));
+        sync();
+      }
+    }
   }
 
   // epilogue: boxed store of this GEMM's share of W
