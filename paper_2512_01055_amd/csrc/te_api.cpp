@@ -500,15 +500,18 @@ struct TimingEvents {
 
 double flops_per_triple(int o, int v) { return 12.0 * (double)v * v * v * ((double)v + o); }
 
+// Triples per launch: at least 64k workgroup tiles (about 85 waves of
+// workgroups over the chip), so that the last, partly filled wave of a
+// launch costs little; W scratch for two batches in flight within 16 GB or
+// an eighth of the budget.
 static int batch_size(const Job &J, Prec p, long ntr) {
   const WConfig wc = wbuild_config(p, J.vp);
   const long mt = ((long)J.vp * J.vp + wc.bm() - 1) / wc.bm();
   const long nt = (J.vp + wc.bn() - 1) / wc.bn();
   const long tiles = 3 * mt * nt;
-  long b = std::max(1L, (16384 + tiles - 1) / tiles);
-  // W scratch for two batches in flight
+  long b = std::max(1L, (65536 + tiles - 1) / tiles);
   const size_t per = 3 * (size_t)J.vp * J.vp * J.vp * out_size(p);
-  const size_t cap = std::max<size_t>(per, (size_t)4 << 30);
+  const size_t cap = std::max<size_t>(per, std::min<size_t>((size_t)16 << 30, J.budget / 8) / 2);
   b = std::min<long>(b, std::max<long>(1, (long)(cap / per)));
   b = std::min<long>(b, ntr);
   return (int)std::max(1L, b);
@@ -881,7 +884,8 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
     const int slot = (int)(b & 1);
     const long first = P.bfirst[b];
     const int cnt = P.bcount[b];
-    if (b >= 2) HIPCHK(hipStreamWaitEvent(J.s_aux, J.ev_e[slot], 0));
+    hipStream_t sw = J.s_aux;
+    if (b >= 2) HIPCHK(hipStreamWaitEvent(sw, J.ev_e[slot], 0));
     // slices this batch needs: assembled on the W stream, after every earlier
     // W build (which may still read the slot being refilled)
     if (fly) HIPCHK(hipEventRecord(ta.start[b], J.s_aux));
@@ -891,11 +895,11 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
       if (J.t2h) fill_panels(J, p, ld.first, sb + x_bytes, sb + x_bytes + col_bytes, J.s_aux);
     }
     if (fly) HIPCHK(hipEventRecord(ta.stop[b], J.s_aux));
-    HIPCHK(hipEventRecord(tw.start[b], J.s_aux));
+    HIPCHK(hipEventRecord(tw.start[b], sw));
     HIPCHK(launch_wbuild(p, witems.as<WItem>() + first, nullptr, cnt, tiles, (long)cnt * tiles,
-                         wc, J.s_aux));
-    HIPCHK(hipEventRecord(tw.stop[b], J.s_aux));
-    HIPCHK(hipEventRecord(J.ev_w[slot], J.s_aux));
+                         wc, sw));
+    HIPCHK(hipEventRecord(tw.stop[b], sw));
+    HIPCHK(hipEventRecord(J.ev_w[slot], sw));
     // the batch's (ov|ov) blocks, on the energy stream while W is built (the
     // energy launch two batches back, the last reader of these blocks, is
     // earlier on the same stream)

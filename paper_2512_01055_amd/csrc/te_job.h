@@ -84,7 +84,7 @@ struct Job {
   int o = 0, v = 0, vp = 0, naux = 0, device = 0;
   te_memkind mem = TE_MEM_HOST;
   bool dev_set = false;
-  hipStream_t s_main = nullptr, s_aux = nullptr;
+  hipStream_t s_main = nullptr, s_aux = nullptr;   // energy and copies; W builds
   bool own_main = false;
   hipEvent_t ev_w[2] = {nullptr, nullptr}, ev_e[2] = {nullptr, nullptr}, ev_start = nullptr;
   size_t budget = 0, used = 0;

@@ -93,8 +93,8 @@ static void run_noalloc(Job &J, Prec p, const int *ijk, long ntr, double *e_sum,
                               std::to_string(kScratchBytes) + "-byte static scratch");
   const long cap = (long)((kScratchBytes - fixed) / per_triple_bytes);   // triples resident
   const int nslot = cap >= 2 ? 2 : 1;
-  // triples per launch: enough tiles to fill the chip (as the allocating
-  // path picks them), within the scratch
+  // triples per launch: at least 16k workgroup tiles (a few waves of
+  // workgroups over the chip), within the scratch
   long B = std::max(1L, (16384L + tiles - 1) / tiles);
   B = std::min(B, std::max(1L, cap / nslot));
   B = std::min(B, ntr);

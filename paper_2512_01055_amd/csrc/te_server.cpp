@@ -117,7 +117,10 @@ struct ServerImpl {
   bool borrow = false;
   int nstage = 2;
   Arena arena;
-  hipStream_t s_w = nullptr, s_e = nullptr;
+  // W builds of consecutive rounds alternate between s_w[0] and s_w[1] (their
+  // outputs are distinct, and one launch's last partial wave of workgroups
+  // then overlaps the next); energy and reductions run on s_e
+  hipStream_t s_w[2] = {nullptr, nullptr}, s_e = nullptr;
   std::vector<hipStream_t> s_stage;   // one staging stream per staging thread
   Slot slot[NSLOT];
   long round = 0;
@@ -240,6 +243,7 @@ void ServerImpl::stage_loop(int q) {
 // Build and launch one packed round into the next slot.
 ServerImpl::Launch ServerImpl::launch_round() {
   Slot &S = slot[round % NSLOT];
+  hipStream_t sw = s_w[round & 1];
   if (S.busy) {
     if (hipEventQuery(S.ev_e) != hipSuccess) return Launch::SlotBusy;
     S.busy = false;
@@ -257,29 +261,18 @@ ServerImpl::Launch ServerImpl::launch_round() {
   if (cand.empty()) return Launch::NoWork;
 
   const int osz = out_bytes(P);
-  // column-block width minimising the padded lone-index work of the round
-  int nb = 5;
-  {
-    long best = -1;
-    for (int c = 8; c >= 4; --c) {
-      long cols = 0;
-      for (SJob *j : cand) {
-        const int vp = j->job->vp;
-        cols += (long)((vp + 16 * c - 1) / (16 * c)) * 16 * c * (long)vp * vp;
-      }
-      if (best < 0 || cols < best) { best = cols; nb = c; }
-    }
-  }
-  WConfig wc = wbuild_config(P, cand.front()->job->vp);
-  wc.nb = nb;
-  const int bm = wc.bm();
-  struct Pick { SJob *j; long t; };
+  // each job keeps the tile shape te_energy uses for its vp (the column-block
+  // count that wastes least of its lone index); the round's W build is one
+  // launch per shape
+  struct Pick { SJob *j; long t; int nb; };
   std::vector<Pick> picks;
   long tiles = 0, blks = 0;
   size_t wbytes = 0;
+  auto cfg_of = [&](SJob *j) { return wbuild_config(P, j->job->vp); };
   auto tiles_of = [&](SJob *j) {
     const long vp = j->job->vp;
-    return 3 * ((vp * vp + bm - 1) / bm) * ((vp + 16 * nb - 1) / (16 * nb));
+    const WConfig c = cfg_of(j);
+    return 3 * ((vp * vp + c.bm() - 1) / c.bm()) * ((vp + c.bn() - 1) / c.bn());
   };
   auto fits = [&](SJob *j) {
     const size_t vp = j->job->vp;
@@ -289,7 +282,7 @@ ServerImpl::Launch ServerImpl::launch_round() {
   };
   auto take = [&](SJob *j) {
     const size_t vp = j->job->vp;
-    picks.push_back({j, j->next});
+    picks.push_back({j, j->next, cfg_of(j).nb});
     tiles += tiles_of(j);
     blks += j->job->nsext;
     wbytes += 3 * vp * vp * vp * osz;
@@ -304,10 +297,14 @@ ServerImpl::Launch ServerImpl::launch_round() {
   for (SJob *j : cand)
     while (j->next < j->ntr && fits(j)) take(j);
   if (picks.empty()) return Launch::NoWork;
+  // items grouped by tile shape (order within a job's triples is kept; each
+  // item's result is independent of its place in the round)
+  std::stable_sort(picks.begin(), picks.end(),
+                   [](const Pick &a, const Pick &b) { return a.nb < b.nb; });
 
   // items and maps in pinned memory
   const int n = (int)picks.size();
-  long t0 = 0, b0 = 0;
+  long b0 = 0;
   size_t woff = 0;
   for (int q = 0; q < n; ++q) {
     SJob *j = picks[q].j;
@@ -327,10 +324,9 @@ ServerImpl::Launch ServerImpl::launch_round() {
     w.xps = op.xps; w.ips = op.ips; w.lo = op.lo; w.scale = op.scale;
     w.W = W; w.o = J.o; w.vp = (int)vp; w.i = i; w.j = jj; w.k = k;
     resident_t2_views(J, op, P, w);
-    w.mt = (int)((vp * vp + bm - 1) / bm);
-    w.nt = (int)((vp + 16 * nb - 1) / (16 * nb));
-    const long nt_ = 3L * w.mt * w.nt;
-    for (long x = 0; x < nt_; ++x) S.h_tmap[t0 + x] = q;
+    WConfig wc = wbuild_config(P, (int)vp);
+    w.mt = (int)((vp * vp + wc.bm() - 1) / wc.bm());
+    w.nt = (int)((vp + wc.bn() - 1) / wc.bn());
     EItem &e = S.h_ei[q];
     e.W = W; resident_k_views(J, i, jj, k, e); e.t1 = J.t1.as<double>();
     e.eo = J.eo.as<double>(); e.ev = J.ev.as<double>(); e.sext = J.sext.as<int>();
@@ -343,24 +339,45 @@ ServerImpl::Launch ServerImpl::launch_round() {
     r.part = e.part; r.part5 = e.part5; r.out = j->eout.as<double>() + t; r.n = J.nsext;
     r.out4 = r.out5 = nullptr;
     r.w = 2.0 - (i == jj) - (jj == k);
-    t0 += nt_;
     b0 += J.nsext;
   }
-  for (int q = 0, acc = 0; q < n; ++q) {  // first tile / block of each item
-    S.h_tmap[t0 + q] = acc;
-    acc += (int)(3L * S.h_wi[q].mt * S.h_wi[q].nt);
+  // tile maps, one region per shape group: [tiles of the group] item (local
+  // to the group) of each tile, then [items of the group] first tile of each
+  struct Group { int q0, nq, nb; long m0, ntl; };
+  std::vector<Group> groups;
+  long moff = 0;
+  for (int q = 0; q < n;) {
+    int qe = q;
+    while (qe < n && picks[qe].nb == picks[q].nb) ++qe;
+    Group G{q, qe - q, picks[q].nb, moff, 0};
+    for (int x = q; x < qe; ++x) G.ntl += 3L * S.h_wi[x].mt * S.h_wi[x].nt;
+    long tt = 0;
+    for (int x = q; x < qe; ++x) {
+      const long nt_ = 3L * S.h_wi[x].mt * S.h_wi[x].nt;
+      for (long y = 0; y < nt_; ++y) S.h_tmap[moff + tt + y] = x - q;
+      S.h_tmap[moff + G.ntl + (x - q)] = (int)tt;
+      tt += nt_;
+    }
+    moff += G.ntl + G.nq;
+    groups.push_back(G);
+    q = qe;
   }
   for (int q = 0, acc = 0; q < n; ++q) {
     S.h_bmap[b0 + q] = acc;
     acc += S.h_ei[q].nsext;
   }
-  HIPCHK(hipMemcpyAsync(S.witems.p, S.h_wi, n * sizeof(WItem), hipMemcpyHostToDevice, s_w));
-  HIPCHK(hipMemcpyAsync(S.tmap.p, S.h_tmap, (t0 + n) * sizeof(int), hipMemcpyHostToDevice, s_w));
-  HIPCHK(hipMemcpyAsync(S.eitems.p, S.h_ei, n * sizeof(EItem), hipMemcpyHostToDevice, s_w));
-  HIPCHK(hipMemcpyAsync(S.ritems.p, S.h_ri, n * sizeof(RItem), hipMemcpyHostToDevice, s_w));
-  HIPCHK(hipMemcpyAsync(S.bmap.p, S.h_bmap, (b0 + n) * sizeof(int), hipMemcpyHostToDevice, s_w));
-  HIPCHK(launch_wbuild(P, S.witems.as<WItem>(), S.tmap.as<int>(), n, 0, t0, wc, s_w));
-  HIPCHK(hipEventRecord(S.ev_w, s_w));
+  HIPCHK(hipMemcpyAsync(S.witems.p, S.h_wi, n * sizeof(WItem), hipMemcpyHostToDevice, sw));
+  HIPCHK(hipMemcpyAsync(S.tmap.p, S.h_tmap, moff * sizeof(int), hipMemcpyHostToDevice, sw));
+  HIPCHK(hipMemcpyAsync(S.eitems.p, S.h_ei, n * sizeof(EItem), hipMemcpyHostToDevice, sw));
+  HIPCHK(hipMemcpyAsync(S.ritems.p, S.h_ri, n * sizeof(RItem), hipMemcpyHostToDevice, sw));
+  HIPCHK(hipMemcpyAsync(S.bmap.p, S.h_bmap, (b0 + n) * sizeof(int), hipMemcpyHostToDevice, sw));
+  for (const Group &G : groups) {
+    WConfig gc = wbuild_config(P, S.h_wi[G.q0].vp);
+    gc.nb = G.nb;
+    HIPCHK(launch_wbuild(P, S.witems.as<WItem>() + G.q0, S.tmap.as<int>() + G.m0, G.nq, 0,
+                         G.ntl, gc, sw));
+  }
+  HIPCHK(hipEventRecord(S.ev_w, sw));
   HIPCHK(hipStreamWaitEvent(s_e, S.ev_w, 0));
   HIPCHK(launch_energy(P == Prec::F64, S.eitems.as<EItem>(), S.bmap.as<int>(), n, 0, b0, s_e));
   HIPCHK(launch_reduce(S.ritems.as<RItem>(), n, s_e));
@@ -448,7 +465,8 @@ void ServerImpl::fail_all(te_status s, const std::string &msg) {
   }
   cv.notify_all();
   (void)hipSetDevice(device);
-  if (s_w) (void)hipStreamSynchronize(s_w);
+  for (hipStream_t st : s_w)
+    if (st) (void)hipStreamSynchronize(st);
   if (s_e) (void)hipStreamSynchronize(s_e);
   std::lock_guard<std::mutex> lk(mu);
   for (auto it = resident.begin(); it != resident.end();) {
@@ -469,7 +487,7 @@ void ServerImpl::fail_all(te_status s, const std::string &msg) {
 
 void ServerImpl::start() {
   HIPCHK(hipSetDevice(device));
-  HIPCHK(hipStreamCreateWithFlags(&s_w, hipStreamNonBlocking));
+  for (hipStream_t &st : s_w) HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&s_e, hipStreamNonBlocking));
   s_stage.assign(nstage, nullptr);
   for (auto &st : s_stage) HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -508,7 +526,8 @@ void ServerImpl::shutdown() {
     if (t.joinable()) t.join();
   if (sched.joinable()) sched.join();
   (void)hipSetDevice(device);
-  if (s_w) (void)hipStreamSynchronize(s_w);
+  for (hipStream_t st : s_w)
+    if (st) (void)hipStreamSynchronize(st);
   if (s_e) (void)hipStreamSynchronize(s_e);
   for (auto st : s_stage)
     if (st) (void)hipStreamSynchronize(st);
@@ -539,7 +558,8 @@ void ServerImpl::shutdown() {
     if (S.ev_e) (void)hipEventDestroy(S.ev_e);
   }
   arena.destroy();
-  if (s_w) (void)hipStreamDestroy(s_w);
+  for (hipStream_t st : s_w)
+    if (st) (void)hipStreamDestroy(st);
   if (s_e) (void)hipStreamDestroy(s_e);
   for (auto st : s_stage)
     if (st) (void)hipStreamDestroy(st);

@@ -1,6 +1,8 @@
 """Serving runtime on the device: packed mixed-job launches give each job the
 same result as a job run alone (bitwise, same precision), admission respects
 the HBM budget, and error paths report the documented statuses."""
+import json
+import os
 import threading
 
 import numpy as np
@@ -19,6 +21,10 @@ def _te():
 # mixed (o, v = 8 o, naux = 3 v) jobs as in the serving workload, small sizes
 MIX = [(8, 64, 192, 101), (5, 40, 120, 102), (10, 80, 240, 103), (8, 64, 192, 104),
        (6, 48, 144, 105), (12, 96, 288, 106), (7, 56, 168, 107), (9, 72, 216, 108)]
+# one job from the middle of the serving workload's size range (o = 8..40)
+MID = (24, 192, 576, 109)
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "serving_jobs.json")
+TOL = {"fp64": 1e-8, "fp32": 1e-6, "bf16x3": 1e-6, "bf16x2": 1e-6, "fp16x2": 1e-6}
 
 
 def _alone(te, P, prec):
@@ -28,16 +34,44 @@ def _alone(te, P, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
 def test_mix_equals_alone_bitwise(prec):
+    """Rounds mix items of different tile shapes (v from 40 to 192): each
+    job's E(T) is still bitwise the one it gets alone."""
     te = _te()
-    probs = [make_problem(*m) for m in MIX]
+    mix = MIX + [MID]
+    probs = [make_problem(*m) for m in mix]
     alone = [_alone(te, P, prec) for P in probs]
     print(f"\n[serving mix of {len(probs)} jobs, {prec}]", flush=True)
     with te.Server(device=0) as srv:
         tickets = [srv.submit(P, prec) for P in probs]
         got = [srv.wait(t) for t in tickets]
-    for (E, st), Ea, m in zip(got, alone, MIX):
+    for (E, st), Ea, m in zip(got, alone, mix):
         assert E == Ea, (m, E, Ea)
         assert st["n_triples"] == te.lib().te_num_triples(m[0])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x2", "fp16x2"])
+def test_served_energies_match_oracle(prec):
+    """Every job of a served mix against stored oracle values of its whole
+    E(T) (written by tests/golden/make_golden.py from the CPU oracle only):
+    FP64 within 1e-11 relative (and the method's 1e-8 Eh bar, read
+    relatively above 1 Eh), reduced precisions within max(1e-6 Eh, 1e-6 |E|)."""
+    if not os.path.exists(GOLDEN):
+        pytest.skip("stored oracle values for the serving jobs are missing")
+    g = json.load(open(GOLDEN))
+    te = _te()
+    probs = [make_problem(j["o"], j["v"], j["naux"], j["seed"], b_std=j["b_std"])
+             for j in g["jobs"]]
+    print(f"\n[served mix of {len(probs)} jobs vs oracle, {prec}]", flush=True)
+    with te.Server(device=0) as srv:
+        tickets = [srv.submit(P, prec) for P in probs]
+        got = [srv.wait(t)[0] for t in tickets]
+    for E, j in zip(got, g["jobs"]):
+        dE = abs(E - j["E"])
+        print(f"o={j['o']} v={j['v']}: E {E:.15e} oracle {j['E']:.15e} |dE| {dE:.2e} "
+              f"rel {dE / abs(j['E']):.2e}")
+        assert dE <= max(TOL[prec], TOL[prec] * abs(j["E"])), (j["o"], E, j["E"])
+        if prec == "fp64":
+            assert dE <= 1e-11 * abs(j["E"]), (j["o"], E, j["E"])
 
 
 def test_mixed_precisions_in_one_server():
