@@ -177,8 +177,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
                 (uintptr_t)(((su.om[1] ? my * vp + mx : mm) * lo + c * EC - lo) * (long)ES);
     }
   }
-  int oB[IB], oI0[IB], oI1[IB];        // element offsets of the lane's B chunk
-                                       // (oI1 is relative to k = lo: may be < 0)
+  // element offsets of the lane's B chunk: in the T2 rows, and (16-bit
+  // occupied phase) from the segment's In row base below
+  int oB[IB], oI[IB];
   int cB[IB], gB[IB], prB[IB];         // k offset; LDS block and part (uniform)
 #pragma unroll
   for (int j = 0; j < IB; ++j) {
@@ -192,9 +193,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
     const long nn = n < vp ? n : 0;
     cB[j] = c * EC;
     oB[j] = (int)(nn * vp + c * EC);
-    oI0[j] = (int)((((long)su.ix[0] * vp + nn) * o + su.iy[0]) * lo + c * EC);
-    oI1[j] = (int)((((long)su.ix[1] * vp + nn) * o + su.iy[1]) * lo + c * EC - lo);
+    oI[j] = (int)(nn * o * lo + c * EC);
   }
+  // In row (ix, n, iy) starts at ((ix vp + n) o + iy) lo; segment 1's base is
+  // taken relative to k = lo
+  const T *IB0 = In + ((long)su.ix[0] * vp * o + su.iy[0]) * lo;
+  const T *IB1 = In + ((long)su.ix[1] * vp * o + su.iy[1]) * lo - lo;
 
   auto dma = [](uintptr_t src, char *dst) __attribute__((always_inline)) {
     __builtin_amdgcn_global_load_lds((gptr<u32x4>)src, (lds_ptr)dst, 16, 0, 0);
@@ -252,7 +256,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
 #pragma unroll
       for (int j = 0; j < IB; ++j) {
         const int k = ko + cB[j];
-        const T *ib = In + prB[j] * w.ips + ko + (k >= lo ? oI1[j] : oI0[j]);
+        const T *ib = (k >= lo ? IB1 : IB0) + prB[j] * w.ips + ko + oI[j];
         dma(k >= KO ? zero : reinterpret_cast<uintptr_t>(ib), sB + gB[j] * 1024);
       }
     }

@@ -413,6 +413,31 @@ def test_host_t2_panels_equal_resident(shape):
             assert np.array_equal(ps, ref[prec][idx])
 
 
+@pytest.mark.parametrize("case", [("small", 6, 30, 90, 1, 0.05), ("physical", 6, 30, 90, 1, 0.0375)],
+                         ids=["small", "physical"])
+@pytest.mark.parametrize("prec", PRECS)
+def test_host_t2_matches_oracle(case, prec):
+    """t2 in host memory (panels streamed into a three-slot cache, so every
+    slot is refilled many times): every triple and E(T) against the CPU
+    oracle directly, with the bars of test_all_triples_match_oracle."""
+    name, o, v, naux, seed, std = case
+    print(f"\n[host t2 {name} o={o} v={v} prec={prec}]", flush=True)
+    P = make_problem(o, v, naux, seed, b_std=std)
+    E_ref, e_ref, _ = oracle_parts(name, P)
+    te = _te()
+    with te.Job(P, device=0, t2_host=True, x_cache_slices=3) as job:
+        E, st, pt = job.energy(prec, per_triple=True)
+    dE = abs(E - E_ref)
+    print(f"E dev {E:.15e} oracle {E_ref:.15e} |dE| {dE:.3e}")
+    assert st["slices_assembled"] > o
+    assert dE <= bar(prec, E_ref)
+    if prec == "fp64":
+        assert dE <= 1e-11 * abs(E_ref)
+        assert np.all(np.abs(pt - e_ref) <= 1e-11 * np.abs(e_ref) + 1e-300)
+    else:
+        assert np.all(np.abs(pt - e_ref) <= TOL[prec] * np.maximum(np.abs(e_ref), 1.0))
+
+
 def test_degenerate_sizes_and_empty_lists():
     """o = 1 has no triples (E = 0); with v = 1 every Z vanishes (a = b = c), so
     E is zero up to rounding, as in the oracle; an empty triple list gives 0."""
