@@ -223,20 +223,27 @@ def bench_serving(args) -> int:
         return time.perf_counter() - t_start, lat
 
     def run_srv(arrivals):
+        """Submit each job at its arrival time and collect results as they
+        complete (every job is reported when it finishes)."""
         lat = [None] * len(os_)
         with te.Server(device=0, borrow_inputs=True, staging_threads=args.staging_threads) as srv:
             t_start = time.perf_counter()
-            tickets = []
-            for q, (o, a) in enumerate(zip(os_, arrivals)):
+            pending = {}
+            nsub, ndone = 0, 0
+            while ndone < len(os_):
                 now = time.perf_counter() - t_start
-                if now < a:
-                    time.sleep(a - now)
-                tickets.append(srv.submit(pool[int(o)], args.precision))
-            for q, t in enumerate(tickets):
-                E, st = srv.wait(t)
-                lat[q] = st["seconds"]
-                log(f"  packed: job {q + 1}/{len(tickets)} (o={int(os_[q])}) collected at "
-                    f"{time.perf_counter() - t_start:.1f} s")
+                while nsub < len(os_) and arrivals[nsub] <= now:
+                    pending[nsub] = srv.submit(pool[int(os_[nsub])], args.precision)
+                    nsub += 1
+                for q in list(pending):
+                    r = srv.poll(pending[q])
+                    if r is not None:
+                        lat[q] = r[1]["seconds"]
+                        del pending[q]
+                        ndone += 1
+                        log(f"  packed: job {q + 1} (o={int(os_[q])}) done at "
+                            f"{time.perf_counter() - t_start:.1f} s ({ndone}/{len(os_)})")
+                time.sleep(0.005)
             span = time.perf_counter() - t_start
         return span, lat
 

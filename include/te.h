@@ -124,10 +124,13 @@ typedef struct te_stats {
   int64_t w_launches;
   double e_kernel_seconds;
   int64_t e_launches;
-  /* On-the-fly (vv|vo) mode: slices assembled, their device time (on the W
-   * stream, ahead of the W builds that read them), and the number of slices
-   * the cache held. The per-triple (ov|ov) blocks run on the energy stream,
-   * overlapped with the W build, and are not part of assemble_seconds. */
+  /* On-the-fly (vv|vo) mode: slices assembled, their device time (on a fill
+   * stream of their own, beside the W builds: each slice is assembled once
+   * the last W build that read its cache slot has finished, and before the
+   * W builds that read it), and the number of slices the cache held. With
+   * t2 in host memory the panel copies are part of the fills. The
+   * per-triple (ov|ov) blocks run on the energy stream, overlapped with the
+   * W build, and are not part of assemble_seconds. */
   int64_t slices_assembled;
   double assemble_seconds;
   int64_t cache_slices;

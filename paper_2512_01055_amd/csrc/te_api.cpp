@@ -632,19 +632,21 @@ static void assemble_slice(Job &J, Prec p, int occ, void *slot, double *tmp64, h
 // column panel and row panel / row form, in the precision the W build reads.
 static void fill_panels(Job &J, Prec p, int occ, char *col, char *row, hipStream_t s) {
   const size_t o = J.o, v2 = (size_t)J.v * J.v;
-  HIPCHK(hipEventSynchronize(J.xc.pinned_free));
+  const int x = J.xc.nfill++ & 1;
+  double *pinned = J.xc.pinned[x];
+  HIPCHK(hipEventSynchronize(J.xc.pinned_free[x]));
   // the o blocks t2[l][occ] are independent: gather them on a few threads
   const size_t nth = std::min<size_t>(o, std::max(1u, std::min(8u, std::thread::hardware_concurrency())));
   auto gather = [&](size_t t) {
     for (size_t l = t; l < o; l += nth)
-      std::memcpy(J.xc.pinned + l * v2, J.t2h + (l * o + (size_t)occ) * v2, v2 * 8);
+      std::memcpy(pinned + l * v2, J.t2h + (l * o + (size_t)occ) * v2, v2 * 8);
   };
   std::vector<std::thread> th;
   for (size_t t = 1; t < nth; ++t) th.emplace_back(gather, t);
   gather(0);
   for (auto &x : th) x.join();
-  HIPCHK(hipMemcpyAsync(J.xc.tstg.p, J.xc.pinned, o * v2 * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(hipEventRecord(J.xc.pinned_free, s));
+  HIPCHK(hipMemcpyAsync(J.xc.tstg.p, pinned, o * v2 * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(J.xc.pinned_free[x], s));
   const int lo = p == Prec::F64 || p == Prec::F32 ? J.o : (J.o + 7) / 8 * 8;
   HIPCHK(launch_panel(p, J.xc.tstg.as<double>(), col, row, J.o, J.v, J.vp, lo,
                       J.op[(int)Prec::FP16X2].sigma_t, s));
@@ -786,8 +788,10 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
       if (J.t2h) {
         const size_t pb = (size_t)o * J.v * J.v * 8;
         J.xc.tstg.alloc(pb, &J.used, J.budget);
-        HIPCHK(hipHostMalloc((void **)&J.xc.pinned, pb, hipHostMallocDefault));
-        HIPCHK(hipEventCreateWithFlags(&J.xc.pinned_free, hipEventDisableTiming));
+        for (int x = 0; x < 2; ++x) {
+          HIPCHK(hipHostMalloc((void **)&J.xc.pinned[x], pb, hipHostMallocDefault));
+          HIPCHK(hipEventCreateWithFlags(&J.xc.pinned_free[x], hipEventDisableTiming));
+        }
       }
       long room = (long)((J.budget - std::min(J.budget, J.used + ((size_t)1 << 28))) / slot_bytes);
       int S = J.x_cache ? J.x_cache : (int)std::min<long>(room, o);
@@ -798,6 +802,7 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
                                   std::to_string(slot_bytes) + " bytes in the HBM budget");
       }
       J.xc.mem.alloc((size_t)S * slot_bytes, &J.used, J.budget);
+      if (!J.xc.s_fill) HIPCHK(hipStreamCreateWithFlags(&J.xc.s_fill, hipStreamNonBlocking));
       J.xc.S = S;
       J.xc.slot_bytes = slot_bytes;
       J.xc.pslot = pslot;
@@ -880,26 +885,42 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
   const bool f64 = p == Prec::F64;
   // timing events around every launch (device time of each kernel)
   TimingEvents tw(nbatch), te_(nbatch), ta(fly ? nbatch : 0);
+  // on-the-fly mode: batch whose W build last read each cache slot (-1:
+  // none in this call; earlier calls have completed)
+  std::vector<long> last_read(fly ? J.xc.S : 0, -1);
   for (long b = 0; b < nbatch; ++b) {
     const int slot = (int)(b & 1);
     const long first = P.bfirst[b];
     const int cnt = P.bcount[b];
     hipStream_t sw = J.s_aux;
     if (b >= 2) HIPCHK(hipStreamWaitEvent(sw, J.ev_e[slot], 0));
-    // slices this batch needs: assembled on the W stream, after every earlier
-    // W build (which may still read the slot being refilled)
-    if (fly) HIPCHK(hipEventRecord(ta.start[b], J.s_aux));
-    for (auto &ld : P.loads[b]) {
-      char *sb = J.xc.mem.as<char>() + (size_t)ld.second * slot_bytes;
-      assemble_slice(J, p, ld.first, sb, J.xc.tmp64.as<double>(), J.s_aux);
-      if (J.t2h) fill_panels(J, p, ld.first, sb + x_bytes, sb + x_bytes + col_bytes, J.s_aux);
+    // slices (and host-t2 panels) this batch needs: filled on the fill
+    // stream, each after the last W build that read its slot (the end-of-
+    // build timing event of that batch), so that fills run ahead of and
+    // beside earlier W builds; this batch's W build waits for them
+    if (fly) {
+      for (auto &ld : P.loads[b]) {
+        const long lr = last_read[ld.second];
+        if (lr >= 0) HIPCHK(hipStreamWaitEvent(J.xc.s_fill, tw.stop[lr], 0));
+      }
+      HIPCHK(hipEventRecord(ta.start[b], J.xc.s_fill));
+      for (auto &ld : P.loads[b]) {
+        char *sb = J.xc.mem.as<char>() + (size_t)ld.second * slot_bytes;
+        assemble_slice(J, p, ld.first, sb, J.xc.tmp64.as<double>(), J.xc.s_fill);
+        if (J.t2h)
+          fill_panels(J, p, ld.first, sb + x_bytes, sb + x_bytes + col_bytes, J.xc.s_fill);
+      }
+      HIPCHK(hipEventRecord(ta.stop[b], J.xc.s_fill));
+      HIPCHK(hipStreamWaitEvent(sw, ta.stop[b], 0));
     }
-    if (fly) HIPCHK(hipEventRecord(ta.stop[b], J.s_aux));
     HIPCHK(hipEventRecord(tw.start[b], sw));
     HIPCHK(launch_wbuild(p, witems.as<WItem>() + first, nullptr, cnt, tiles, (long)cnt * tiles,
                          wc, sw));
     HIPCHK(hipEventRecord(tw.stop[b], sw));
     HIPCHK(hipEventRecord(J.ev_w[slot], sw));
+    if (fly)   // the slots this batch's W build reads
+      for (int q = 0; q < cnt; ++q)
+        for (int d = 0; d < 3; ++d) last_read[P.slot[first + q][d]] = b;
     // the batch's (ov|ov) blocks, on the energy stream while W is built (the
     // energy launch two batches back, the last reader of these blocks, is
     // earlier on the same stream)
@@ -980,24 +1001,29 @@ Job::~Job() {
   if (ev_start) (void)hipEventDestroy(ev_start);
   if (own_main && s_main) (void)hipStreamDestroy(s_main);
   xc.release();
+  if (xc.s_fill) (void)hipStreamDestroy(xc.s_fill);
 }
 
 void Job::SliceCache::release() {
+  if (s_fill) (void)hipStreamSynchronize(s_fill);   // fills in flight finish first
   mem.release();
   tmp64.release();
   tstg.release();
   held.clear();
   S = 0;
   pslot = -1;
-  if (pinned_free) {
-    (void)hipEventSynchronize(pinned_free);
-    (void)hipEventDestroy(pinned_free);
-    pinned_free = nullptr;
+  for (int x = 0; x < 2; ++x) {
+    if (pinned_free[x]) {
+      (void)hipEventSynchronize(pinned_free[x]);
+      (void)hipEventDestroy(pinned_free[x]);
+      pinned_free[x] = nullptr;
+    }
+    if (pinned[x]) {
+      (void)hipHostFree(pinned[x]);
+      pinned[x] = nullptr;
+    }
   }
-  if (pinned) {
-    (void)hipHostFree(pinned);
-    pinned = nullptr;
-  }
+  nfill = 0;
 }
 
 static void check_problem(const te_problem *P) {

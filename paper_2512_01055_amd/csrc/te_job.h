@@ -111,11 +111,15 @@ struct Job {
     size_t slot_bytes = 0;
     DBuf mem, tmp64;
     std::vector<int> held;
-    // host t2: FP64 column panel on the device, its pinned host bounce
-    // buffer, and the event after which the bounce buffer may be refilled
+    // host t2: FP64 column panel on the device, two pinned host bounce
+    // buffers used in turn, and the events after which each may be refilled
     DBuf tstg;
-    double *pinned = nullptr;
-    hipEvent_t pinned_free = nullptr;
+    double *pinned[2] = {nullptr, nullptr};
+    hipEvent_t pinned_free[2] = {nullptr, nullptr};
+    int nfill = 0;                // panel fills so far (selects the bounce buffer)
+    // stream the slices and panels are filled on, ahead of the W builds:
+    // a fill waits only for the last W build that read its slot
+    hipStream_t s_fill = nullptr;
     void release();
   } xc;
   int nT = 0, nsext = 0;

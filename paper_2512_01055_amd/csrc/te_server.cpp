@@ -4,9 +4,10 @@
 // footprint fits a server-wide arena, staged by a staging thread (integral
 // assembly and precision copies on their own stream, overlapping the compute
 // of resident jobs), and their occupied triples are packed with those of every
-// other resident job of the same precision into shared launches: one W-build
-// launch and one energy launch per round, mapping tiles and sextet blocks to
-// (job, triple) items. Three rounds are in flight at once (three scratch slots).
+// other resident job of the same precision into shared launches (filled
+// shortest remaining work first): one W-build launch per tile shape and one
+// energy launch per round, mapping tiles and sextet blocks to (job, triple)
+// items. Three rounds are in flight at once (three scratch slots).
 // A job finishes with a fixed-order sum of its per-triple partials, so its
 // result is bitwise the one te_energy computes for it alone.
 #include <hip/hip_runtime.h>
@@ -117,10 +118,11 @@ struct ServerImpl {
   bool borrow = false;
   int nstage = 2;
   Arena arena;
-  // W builds of consecutive rounds alternate between s_w[0] and s_w[1] (their
-  // outputs are distinct, and one launch's last partial wave of workgroups
-  // then overlaps the next); energy and reductions run on s_e
-  hipStream_t s_w[2] = {nullptr, nullptr}, s_e = nullptr;
+  // W builds on s_w, energy and reductions on s_e. (Two W streams, letting
+  // a round's last partial wave of workgroups overlap the next round,
+  // measured slower: concurrent W builds of different rounds share L2 and
+  // slow the energy launches beside them more than the tails cost.)
+  hipStream_t s_w[1] = {nullptr}, s_e = nullptr;
   std::vector<hipStream_t> s_stage;   // one staging stream per staging thread
   Slot slot[NSLOT];
   long round = 0;
@@ -243,7 +245,7 @@ void ServerImpl::stage_loop(int q) {
 // Build and launch one packed round into the next slot.
 ServerImpl::Launch ServerImpl::launch_round() {
   Slot &S = slot[round % NSLOT];
-  hipStream_t sw = s_w[round & 1];
+  hipStream_t sw = s_w[0];
   if (S.busy) {
     if (hipEventQuery(S.ev_e) != hipSuccess) return Launch::SlotBusy;
     S.busy = false;
@@ -288,14 +290,18 @@ ServerImpl::Launch ServerImpl::launch_round() {
     wbytes += 3 * vp * vp * vp * osz;
     j->next++;
   };
-  // fair share first, then fill in arrival order
-  const long share = std::max(1L, MAX_TILES / (long)cand.size());
-  for (SJob *j : cand) {
-    long got = 0;
-    while (j->next < j->ntr && got < share && fits(j)) { got += tiles_of(j); take(j); }
-  }
-  for (SJob *j : cand)
-    while (j->next < j->ntr && fits(j)) take(j);
+  // shortest remaining work first: small jobs finish within a round or two,
+  // and the rest of a round goes to the resident job closest to done. Rounds
+  // then mostly hold one large job's triples in its i-major order, so its X
+  // slices stay hot in L2 and the MALL across rounds, as in a job run alone
+  // (mixing many large jobs in every round costs the L2-bound 16-bit W
+  // builds several percent).
+  std::vector<std::pair<long, SJob *>> order;
+  for (SJob *j : cand) order.push_back({(j->ntr - j->next) * tiles_of(j), j});
+  std::stable_sort(order.begin(), order.end(),
+                   [](const auto &a, const auto &b) { return a.first < b.first; });
+  for (auto &oj : order)
+    while (oj.second->next < oj.second->ntr && fits(oj.second)) take(oj.second);
   if (picks.empty()) return Launch::NoWork;
   // items grouped by tile shape (order within a job's triples is kept; each
   // item's result is independent of its place in the round)
@@ -491,7 +497,9 @@ void ServerImpl::start() {
   HIPCHK(hipStreamCreateWithFlags(&s_e, hipStreamNonBlocking));
   s_stage.assign(nstage, nullptr);
   for (auto &st : s_stage) HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-  wcap = std::min<size_t>((size_t)3 << 30, budget / 8);
+  // W scratch per round slot: large rounds keep the last, partly filled
+  // wave of workgroups a small share of each W launch
+  wcap = std::min<size_t>((size_t)8 << 30, budget / 12);
   for (Slot &S : slot) {
     S.W.alloc(wcap, nullptr, 0);
     S.part.alloc(2 * (size_t)MAX_BLKS * 8, nullptr, 0);
