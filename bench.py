@@ -254,6 +254,26 @@ def bench_serving(args) -> int:
                 "p99_s": round(float(np.percentile(lat, 99)), 3)}
 
     out = {}
+    if args.arrivals == "poisson":
+        if args.rate <= 0:
+            raise SystemExit("--arrivals poisson needs --rate")
+        arr = np.cumsum(rng.exponential(1.0 / args.rate, size=args.jobs))
+        log(f"serving: Poisson arrivals at {args.rate:.3f} jobs/s, sequential")
+        span_seq2, lat_seq2 = run_seq(arr)
+        log("serving: Poisson arrivals, packed server")
+        span_p2, lat_p2 = run_srv(arr)
+        out["poisson"] = {"rate_jobs_per_s": round(args.rate, 4),
+                          "sequential": summary(span_seq2, lat_seq2),
+                          "packed": summary(span_p2, lat_p2)}
+        print(json.dumps({"metric": "(T) serving mix: jobs/s and p50/p99 latency, packed vs "
+                                    "sequential", "value": out["poisson"]["packed"]["jobs_per_s"],
+                          "unit": "jobs/s", "n_gpus": 1, "data": "synthetic",
+                          "precision": args.precision,
+                          "config": {"workload": f"{args.jobs} (T) jobs, o ~ U{{{args.omin}.."
+                                                 f"{args.omax}}}, v = 8 o, naux = 3 v, seed 4; "
+                                                 f"{work:.3e} flop in total"},
+                          "results": out}), flush=True)
+        return 0
     sat = np.zeros(args.jobs)
     log("serving: saturated arrivals, sequential")
     span_seq, lat_seq = run_seq(sat)
@@ -307,8 +327,11 @@ def main() -> int:
     ap.add_argument("--omax", type=int, default=40)
     ap.add_argument("--precision", default="fp64", help="serving: precision of every job")
     ap.add_argument("--staging-threads", type=int, default=2, help="serving: concurrent staging")
-    ap.add_argument("--arrivals", choices=("both", "saturated"), default="both",
-                    help="serving: saturated only, or also Poisson at 0.8 x sequential capacity")
+    ap.add_argument("--arrivals", choices=("both", "saturated", "poisson"), default="both",
+                    help="serving: saturated only, also Poisson at 0.8 x sequential capacity, "
+                         "or Poisson only at --rate")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="serving, --arrivals poisson: arrival rate in jobs/s")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size copy "
                          "kernel for scaling hardware byte counters)")
