@@ -4,8 +4,8 @@
 // footprint fits a server-wide arena, staged by a staging thread (integral
 // assembly and precision copies on their own stream, overlapping the compute
 // of resident jobs), and their occupied triples are packed with those of every
-// other resident job of the same precision into shared launches (filled
-// shortest remaining work first): one W-build launch per tile shape and one
+// other resident job of the same precision into shared launches (small jobs
+// first, then large ones in admission order): one W-build launch per tile shape and one
 // energy launch per round, mapping tiles and sextet blocks to (job, triple)
 // items. Three rounds are in flight at once (three scratch slots).
 // A job finishes with a fixed-order sum of its per-triple partials, so its
@@ -290,18 +290,27 @@ ServerImpl::Launch ServerImpl::launch_round() {
     wbytes += 3 * vp * vp * vp * osz;
     j->next++;
   };
-  // shortest remaining work first: small jobs finish within a round or two,
-  // and the rest of a round goes to the resident job closest to done. Rounds
-  // then mostly hold one large job's triples in its i-major order, so its X
-  // slices stay hot in L2 and the MALL across rounds, as in a job run alone
-  // (mixing many large jobs in every round costs the L2-bound 16-bit W
-  // builds several percent).
-  std::vector<std::pair<long, SJob *>> order;
-  for (SJob *j : cand) order.push_back({(j->ntr - j->next) * tiles_of(j), j});
-  std::stable_sort(order.begin(), order.end(),
+  // Small jobs first (those whose remaining work fits a quarter of a round,
+  // smallest first): they finish within a round or two. The rest of a round
+  // goes to the large jobs in admission order, so a round mostly holds one
+  // large job's triples in its i-major order (its X slices stay hot in L2
+  // and the MALL across rounds, as in a job run alone) and no large job is
+  // overtaken by a later one. (Every resident job in every round cost the
+  // 16-bit W build and the energy kernel up to 2x their time alone; pure
+  // shortest-remaining-work-first let later large jobs starve earlier ones
+  // under Poisson arrivals.)
+  std::vector<std::pair<long, SJob *>> small;
+  std::vector<SJob *> large;
+  for (SJob *j : cand) {   // cand is in admission order
+    const long rem = (j->ntr - j->next) * tiles_of(j);
+    if (rem <= MAX_TILES / 4) small.push_back({rem, j}); else large.push_back(j);
+  }
+  std::stable_sort(small.begin(), small.end(),
                    [](const auto &a, const auto &b) { return a.first < b.first; });
-  for (auto &oj : order)
-    while (oj.second->next < oj.second->ntr && fits(oj.second)) take(oj.second);
+  for (auto &sj : small)
+    while (sj.second->next < sj.second->ntr && fits(sj.second)) take(sj.second);
+  for (SJob *j : large)
+    while (j->next < j->ntr && fits(j)) take(j);
   if (picks.empty()) return Launch::NoWork;
   // items grouped by tile shape (order within a job's triples is kept; each
   // item's result is independent of its place in the round)
