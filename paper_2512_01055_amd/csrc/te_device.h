@@ -120,6 +120,11 @@ template <typename T> struct Chunk {
   }
 };
 
+// Choice between two values. A conditional over two lvalues (array elements,
+// struct members) is one over their addresses, which can send the whole
+// array or struct to scratch memory; this one is over the loaded values.
+template <typename T> __device__ inline T pick(bool c, T a, T b) { return c ? a : b; }
+
 __device__ inline d4 mma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }

@@ -2,12 +2,15 @@
 //
 //  energy_kernel   V (Eq. 3), D (Eq. 4, sign of the energy-kernel figure), the
 //                  permutation combination Z and (W + V) Z / D of Eq. 1, over
-//                  one sextet of 8^3 W boxes per workgroup.
+//                  sextets of 8^3 W boxes (up to eight per workgroup, the next
+//                  one's loads in flight while one is evaluated).
 //  reduce/sum      fixed-order FP64 reductions (bitwise reproducible).
 //  gemm_tn         FP64 MFMA product used to assemble integrals from the
 //                  factors (Eq. 6) at staging.
 //  conversions     FP64 -> FP32 and FP64 -> split BF16 operand copies.
 #include "te_device.h"
+
+#include <algorithm>
 
 namespace te {
 namespace {
@@ -29,153 +32,237 @@ constexpr int BX_S = 8 * BX_P;      // slot size in doubles
 
 __device__ inline int bxi(int x0, int x1, int x2) { return x0 * BX_P + x1 * BX_R + x2; }
 
-template <typename WT>
-__global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ items,
-                                                    const int *__restrict__ blk_item,
-                                                    int blks_per_item, long total) {
-  __shared__ double box[6 * BX_S];
-  __shared__ double kst[6 * 3 * BOX * BOX];
-  __shared__ double vst[4 * 3 * BOX];
-  __shared__ double red[2 * (WG / 64)];
-  const int tid = threadIdx.x;
-  const long bid = blockIdx.x;
-  int it;
-  long local;
-  if (blk_item) {
-    it = blk_item[bid];
-    local = bid - blk_item[total + it];
-  } else {
-    it = (int)(bid / blks_per_item);
-    local = bid - (long)it * blks_per_item;
+// N uniform ints read at an index known only at run time. The selects keep
+// them in scalar registers, where an indexed array would go to scratch memory.
+template <int N> struct Sel {
+  int c[N];
+  __device__ int operator[](int q) const {
+    int r = c[0];
+#pragma unroll
+    for (int m = 1; m < N; ++m) r = pick(q == m, c[m], r);
+    return r;
   }
-  const EItem &e = items[it];
-  const int v = e.v, vp = e.vp, nT = e.nT;
-  const int i = e.i, j = e.j, k = e.k;
-  const int packed = e.sext[local];
-  int T[3] = {packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023};
+};
 
+// One sextet as the kernel sees it: where its item's arrays are, which of the
+// item's sextets it is, its box indices (A, B, C), the first slot holding each
+// slot's box (slots repeat when A, B, C are not all different), and the
+// occupied part of D. Everything here is uniform over the workgroup; slot s
+// holds box (T[c_perm[s][0]], T[c_perm[s][1]], T[c_perm[s][2]]).
+struct Sext {
+  const void *W;
+  const double *Kjk, *Kik, *Kij, *t1, *ev;
+  double *part, *part5;
+  long kld, local;
+  int v, vp, nT, i, j, k;
+  Sel<3> T;
+  Sel<6> canon;
+  double eijk;
+};
+
+// Read-only views in the constant address space: uniform loads through them
+// become scalar loads, which the wave does not wait for at its vector-load
+// counter (the next sextet's W loads stay in flight behind them).
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+
+__device__ inline void sext_at(long g, const EItem *items, const int *blk_item,
+                               int blks_per_item, long total, Sext &x) {
+  int it;
+  if (blk_item) {
+    it = ((cptr<int>)blk_item)[g];
+    x.local = g - ((cptr<int>)blk_item)[total + it];
+  } else {
+    it = (int)(g / blks_per_item);
+    x.local = g - (long)it * blks_per_item;
+  }
+  cptr<EItem> e = (cptr<EItem>)items + it;
+  x.W = e->W; x.Kjk = e->Kjk; x.Kik = e->Kik; x.Kij = e->Kij; x.kld = e->kld;
+  x.t1 = e->t1; x.ev = e->ev; x.part = e->part; x.part5 = e->part5;
+  x.v = e->v; x.vp = e->vp; x.nT = e->nT; x.i = e->i; x.j = e->j; x.k = e->k;
+  const int packed = ((cptr<int>)e->sext)[x.local];
+  x.T.c[0] = packed & 1023; x.T.c[1] = (packed >> 10) & 1023; x.T.c[2] = (packed >> 20) & 1023;
   int bx[6][3];
-  int canon[6];
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
-    bx[s][0] = T[c_perm[s][0]]; bx[s][1] = T[c_perm[s][1]]; bx[s][2] = T[c_perm[s][2]];
-    canon[s] = s;
-    for (int q = 0; q < s; ++q)
-      if (canon[s] == s && bx[q][0] == bx[s][0] && bx[q][1] == bx[s][1] && bx[q][2] == bx[s][2])
-        canon[s] = q;
-  }
-
-  const long vp3 = (long)vp * vp * vp;
-  const WT *W0 = reinterpret_cast<const WT *>(e.W);
-  const WT *W1 = W0 + vp3;
-  const WT *W2 = W1 + vp3;
-  // every load of the thread is issued before the first LDS store (one
-  // memory latency per workgroup, not one per element); element u of the
-  // thread is element tid + 256 (u % 2) of slot u / 2
-  constexpr int PER = 6 * BOX3 / WG;
-  double wv[PER];
+    bx[s][0] = x.T[c_perm[s][0]]; bx[s][1] = x.T[c_perm[s][1]]; bx[s][2] = x.T[c_perm[s][2]];
+    x.canon.c[s] = s;
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int s = u >> 1, r = tid + WG * (u & 1);
-    wv[u] = 0.0;
-    if (canon[s] == s) {
-      const long base = ((((long)bx[s][0] * nT + bx[s][1]) * nT + bx[s][2]) << 9) + r;
-      wv[u] = ((double)gld(W0 + base) + (double)gld(W1 + base)) + (double)gld(W2 + base);
-    }
+    for (int q = 0; q < s; ++q)
+      if (x.canon.c[s] == s && bx[q][0] == bx[s][0] && bx[q][1] == bx[s][1] &&
+          bx[q][2] == bx[s][2])
+        x.canon.c[s] = q;
   }
-  // The inputs of V and D go to LDS in the same pass: per slot the 8 x 8
-  // blocks of (jb|kc), (ia|kc) and (ia|jb) it reads (kst[s][0..2][row][col]),
-  // and per box index T[m] the eight t1 entries of rows i, j, k and the eight
-  // virtual orbital energies (vst[0..3][m][x]). Box indices are below vp / 8,
-  // so every one of these loads is inside the padded arrays.
-  // Thread tid < KB holds value tid of every slot's K blocks; the slot loop is
-  // unrolled and the box index chosen by selects, so that no private array
-  // is indexed per lane.
-  constexpr int KB = 3 * BOX * BOX, NV = 4 * 3 * BOX;
-  double kv[6];
+  cptr<double> eo = (cptr<double>)e->eo;
+  x.eijk = (eo[x.i] + eo[x.j]) + eo[x.k];
+}
+
+// element u of a thread is element tid + 256 (u % 2) of slot u / 2
+constexpr int EPER = 6 * BOX3 / WG;
+constexpr int EKB = 3 * BOX * BOX, ENV = 4 * 3 * BOX;
+
+// Issue the loads of one sextet: the inputs of V and D (per slot the 8 x 8
+// blocks of (jb|kc), (ia|kc) and (ia|jb) it reads; per box index T[m] the
+// eight t1 entries of rows i, j, k and the eight virtual orbital energies),
+// then the three W shares of each distinct box. Box indices are below vp / 8, so
+// every load is inside the padded arrays. Thread tid < EKB holds value tid of
+// every slot's K blocks; the slot loop is unrolled and the box index chosen
+// by selects, so that no private array is indexed per lane.
+template <typename WT>
+__device__ inline void sext_load(const Sext &x, int tid, WT (&w)[3][EPER], double (&kv)[6],
+                                 double &tv) {
   {
     const int mat = tid >> 6, p = (tid >> 3) & 7, r = tid & 7;
-    const double *Km = mat == 0 ? e.Kjk : (mat == 1 ? e.Kik : e.Kij);
+    const double *Km = pick(mat == 0, x.Kjk, pick(mat == 1, x.Kik, x.Kij));
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       kv[s] = 0.0;
-      if (tid < KB && canon[s] == s) {
-        const int rb = mat == 0 ? bx[s][1] : bx[s][0];   // rows: b, a, a
-        const int cb = mat == 2 ? bx[s][1] : bx[s][2];   // columns: c, c, b
-        kv[s] = gld(Km + (long)(rb * BOX + p) * e.kld + cb * BOX + r);
+      if (tid < EKB && x.canon.c[s] == s) {
+        const int b0 = x.T[c_perm[s][0]], b1 = x.T[c_perm[s][1]], b2 = x.T[c_perm[s][2]];
+        const int rb = pick(mat == 0, b1, b0);   // rows: b, a, a
+        const int cb = pick(mat == 2, b1, b2);   // columns: c, c, b
+        kv[s] = gld(Km + (long)(rb * BOX + p) * x.kld + cb * BOX + r);
       }
     }
   }
-  double tv = 0.0;
-  if (tid < NV) {
-    const int w = tid / (3 * BOX), m = (tid / BOX) % 3;
-    const int x = (m == 0 ? T[0] : (m == 1 ? T[1] : T[2])) * BOX + (tid & 7);
-    tv = w == 3 ? gld(e.ev + x) : gld(e.t1 + (long)(w == 0 ? i : (w == 1 ? j : k)) * vp + x);
+  tv = 0.0;
+  if (tid < ENV) {
+    const int wq = tid / (3 * BOX), m = (tid / BOX) % 3;
+    const int xi = x.T[m] * BOX + (tid & 7);
+    const int row = pick(wq == 0, x.i, pick(wq == 1, x.j, x.k));
+    tv = wq == 3 ? gld(x.ev + xi) : gld(x.t1 + (long)row * x.vp + xi);
   }
+  const long vp3 = (long)x.vp * x.vp * x.vp;
+  const WT *W0 = reinterpret_cast<const WT *>(x.W);
+  const WT *W1 = W0 + vp3;
+  const WT *W2 = W1 + vp3;
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
+  for (int u = 0; u < EPER; ++u) {
     const int s = u >> 1, r = tid + WG * (u & 1);
-    if (canon[s] == s) box[s * BX_S + bxi(r >> 6, (r >> 3) & 7, r & 7)] = wv[u];
+    w[0][u] = w[1][u] = w[2][u] = WT(0);
+    if (x.canon.c[s] == s) {
+      const int b0 = x.T[c_perm[s][0]], b1 = x.T[c_perm[s][1]], b2 = x.T[c_perm[s][2]];
+      const long base = ((((long)b0 * x.nT + b1) * x.nT + b2) << 9) + r;
+      w[0][u] = gld(W0 + base);
+      w[1][u] = gld(W1 + base);
+      w[2][u] = gld(W2 + base);
+    }
   }
-  if (tid < KB) {
-#pragma unroll
-    for (int s = 0; s < 6; ++s) kst[s * KB + tid] = kv[s];
-  }
-  if (tid < NV) vst[tid] = tv;
-  __syncthreads();
+}
 
-  const double eijk = (e.eo[i] + e.eo[j]) + e.eo[k];
-  double acc4 = 0.0, acc5 = 0.0;   // W Z / D and V Z / D (E[4] and E[5] parts)
+// Workgroup barrier ordering LDS accesses only: the wave waits for its own
+// LDS accesses but not for its global loads (a __syncthreads would), so the
+// next sextet's loads stay in flight across it.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Each workgroup evaluates es consecutive sextets of the launch's sextet list
+// (global ids across items). The loads of sextet n+1 are issued right after
+// sextet n is staged in LDS, so they are in flight while sextet n is
+// evaluated from LDS. The arithmetic of each sextet, and its partial sums, do
+// not depend on es.
+template <typename WT>
+__global__ __launch_bounds__(WG) void energy_kernel(const EItem *__restrict__ items,
+                                                    const int *__restrict__ blk_item,
+                                                    int blks_per_item, long total, int es) {
+  __shared__ double box[6 * BX_S];
+  __shared__ double kst[6 * EKB];
+  __shared__ double vst[ENV];
+  __shared__ double red[2 * (WG / 64)];
+  const int tid = threadIdx.x;
+  const long g0 = (long)blockIdx.x * es;
+  const int cnt = (int)(total - g0 < es ? total - g0 : es);
+
+  WT w[3][EPER];
+  double kv[6], tv;
+  Sext cur;
+  sext_at(g0, items, blk_item, blks_per_item, total, cur);
+  sext_load(cur, tid, w, kv, tv);
+
+  for (int n = 0; n < cnt; ++n) {
+    // stage sextet n: the three W shares summed into the padded boxes
+#pragma unroll
+    for (int u = 0; u < EPER; ++u) {
+      const int s = u >> 1, r = tid + WG * (u & 1);
+      if (cur.canon.c[s] == s)
+        box[s * BX_S + bxi(r >> 6, (r >> 3) & 7, r & 7)] =
+            ((double)w[0][u] + (double)w[1][u]) + (double)w[2][u];
+    }
+    if (tid < EKB) {
+#pragma unroll
+      for (int s = 0; s < 6; ++s) kst[s * EKB + tid] = kv[s];
+    }
+    if (tid < ENV) vst[tid] = tv;
+    lds_barrier();
+
+    Sext nxt = cur;
+    if (n + 1 < cnt) {
+      sext_at(g0 + n + 1, items, blk_item, blks_per_item, total, nxt);
+      sext_load(nxt, tid, w, kv, tv);
+    }
+
+    const int v = cur.v;
+    const Sel<3> &T = cur.T;
+    const Sel<6> &canon = cur.canon;
+    double acc4 = 0.0, acc5 = 0.0;   // W Z / D and V Z / D (E[4] and E[5] parts)
 #pragma unroll 1
-  for (int s = 0; s < 6; ++s) {
-    if (canon[s] != s) continue;
-    const int sb = canon[c_comp[s][3]] * BX_S;  // (b,c,a)
-    const int sc = canon[c_comp[s][5]] * BX_S;  // (c,a,b)
-    const int sd = canon[c_comp[s][1]] * BX_S;  // (a,c,b)
-    const int se = canon[c_comp[s][2]] * BX_S;  // (b,a,c)
-    const int sf = canon[c_comp[s][4]] * BX_S;  // (c,b,a)
-    const double *ks = kst + s * KB;
-    const double *va = vst + c_perm[s][0] * BOX, *vb = vst + c_perm[s][1] * BOX,
-                 *vc = vst + c_perm[s][2] * BOX;
-    for (int r = tid; r < BOX3; r += WG) {
-      const int x0 = r >> 6, x1 = (r >> 3) & 7, x2 = r & 7;
-      const int a = bx[s][0] * 8 + x0, b = bx[s][1] * 8 + x1, c = bx[s][2] * 8 + x2;
-      if (a < v && b < v && c < v) {
-        const double w0 = box[s * BX_S + bxi(x0, x1, x2)];
-        const double z = 4.0 * w0 + box[sb + bxi(x1, x2, x0)] + box[sc + bxi(x2, x0, x1)]
-                         - 2.0 * box[sd + bxi(x0, x2, x1)] - 2.0 * box[se + bxi(x1, x0, x2)]
-                         - 2.0 * box[sf + bxi(x2, x1, x0)];
-        // singles term (Eq. 3): t_i^a (jb|kc) + t_j^b (ia|kc) + t_k^c (ia|jb)
-        const double vt = va[x0] * ks[x1 * BOX + x2]
-                        + vb[3 * BOX + x1] * ks[BOX * BOX + x0 * BOX + x2]
-                        + vc[6 * BOX + x2] * ks[2 * BOX * BOX + x0 * BOX + x1];
-        const double d = ((eijk - va[9 * BOX + x0]) - vb[9 * BOX + x1]) - vc[9 * BOX + x2];
-        const double q = z / d;
-        acc4 += w0 * q;
-        acc5 += vt * q;
+    for (int s = 0; s < 6; ++s) {
+      if (canon[s] != s) continue;
+      const int sb = canon[c_comp[s][3]] * BX_S;  // (b,c,a)
+      const int sc = canon[c_comp[s][5]] * BX_S;  // (c,a,b)
+      const int sd = canon[c_comp[s][1]] * BX_S;  // (a,c,b)
+      const int se = canon[c_comp[s][2]] * BX_S;  // (b,a,c)
+      const int sf = canon[c_comp[s][4]] * BX_S;  // (c,b,a)
+      const double *ks = kst + s * EKB;
+      const double *va = vst + c_perm[s][0] * BOX, *vb = vst + c_perm[s][1] * BOX,
+                   *vc = vst + c_perm[s][2] * BOX;
+      const int a0 = T[c_perm[s][0]] * 8, b0 = T[c_perm[s][1]] * 8, c0 = T[c_perm[s][2]] * 8;
+      for (int r = tid; r < BOX3; r += WG) {
+        const int x0 = r >> 6, x1 = (r >> 3) & 7, x2 = r & 7;
+        const int a = a0 + x0, b = b0 + x1, c = c0 + x2;
+        if (a < v && b < v && c < v) {
+          const double w0 = box[s * BX_S + bxi(x0, x1, x2)];
+          const double z = 4.0 * w0 + box[sb + bxi(x1, x2, x0)] + box[sc + bxi(x2, x0, x1)]
+                           - 2.0 * box[sd + bxi(x0, x2, x1)] - 2.0 * box[se + bxi(x1, x0, x2)]
+                           - 2.0 * box[sf + bxi(x2, x1, x0)];
+          // singles term (Eq. 3): t_i^a (jb|kc) + t_j^b (ia|kc) + t_k^c (ia|jb)
+          const double vt = va[x0] * ks[x1 * BOX + x2]
+                          + vb[3 * BOX + x1] * ks[BOX * BOX + x0 * BOX + x2]
+                          + vc[6 * BOX + x2] * ks[2 * BOX * BOX + x0 * BOX + x1];
+          const double d = ((cur.eijk - va[9 * BOX + x0]) - vb[9 * BOX + x1]) - vc[9 * BOX + x2];
+          const double q = z / d;
+          acc4 += w0 * q;
+          acc5 += vt * q;
+        }
       }
     }
-  }
-  // fixed-order reduction: butterfly within the wave, then waves in order
+    // fixed-order reduction: butterfly within the wave, then waves in order
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    acc4 += __shfl_xor(acc4, off, 64);
-    acc5 += __shfl_xor(acc5, off, 64);
-  }
-  if ((tid & 63) == 0) {
-    red[tid >> 6] = acc4;
-    red[WG / 64 + (tid >> 6)] = acc5;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double s4 = red[0], s5 = red[WG / 64];
-#pragma unroll
-    for (int q = 1; q < WG / 64; ++q) {
-      s4 += red[q];
-      s5 += red[WG / 64 + q];
+    for (int off = 32; off > 0; off >>= 1) {
+      acc4 += __shfl_xor(acc4, off, 64);
+      acc5 += __shfl_xor(acc5, off, 64);
     }
-    gst(e.part + local, s4);
-    gst(e.part5 + local, s5);
+    if ((tid & 63) == 0) {
+      red[tid >> 6] = acc4;
+      red[WG / 64 + (tid >> 6)] = acc5;
+    }
+    // every wave is done with the boxes of sextet n past this barrier; thread
+    // 0 reads red before it reaches the next one, and red is written again
+    // only after it
+    lds_barrier();
+    if (tid == 0) {
+      double s4 = red[0], s5 = red[WG / 64];
+#pragma unroll
+      for (int q = 1; q < WG / 64; ++q) {
+        s4 += red[q];
+        s5 += red[WG / 64 + q];
+      }
+      gst(cur.part + cur.local, s4);
+      gst(cur.part5 + cur.local, s5);
+    }
+    cur = nxt;
   }
 }
 
@@ -573,11 +660,16 @@ hipError_t launch_energy(bool w_is_f64, const EItem *d_items, const int *d_blk_i
   (void)nitems;
   if (total_blks <= 0) return hipSuccess;
   if (total_blks > 0x7fffffffL) return hipErrorInvalidValue;
-  dim3 grid((unsigned)total_blks), block(WG);
+  // sextets per workgroup: 8, or fewer while that leaves under 4096
+  // workgroups (about four per CU slot), so small launches still fill the chip
+  const int es = (int)std::max(1L, std::min(8L, total_blks / 4096));
+  dim3 grid((unsigned)((total_blks + es - 1) / es)), block(WG);
   if (w_is_f64)
-    energy_kernel<double><<<grid, block, 0, s>>>(d_items, d_blk_item, blks_per_item, total_blks);
+    energy_kernel<double><<<grid, block, 0, s>>>(d_items, d_blk_item, blks_per_item, total_blks,
+                                                 es);
   else
-    energy_kernel<float><<<grid, block, 0, s>>>(d_items, d_blk_item, blks_per_item, total_blks);
+    energy_kernel<float><<<grid, block, 0, s>>>(d_items, d_blk_item, blks_per_item, total_blks,
+                                                es);
   return hipGetLastError();
 }
 

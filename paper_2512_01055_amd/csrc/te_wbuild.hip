@@ -453,28 +453,46 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
     }
   }
 
-  // epilogue: boxed store of this GEMM's share of W
+  // epilogue: boxed store of this GEMM's share of W, with one division per
+  // output row. Store order: row by row for FP64 (ROWQ = 1); for the FP32
+  // outputs a 16 x 16 block at a time (four stores cover it: rows 4 (l / 16)
+  // + r), which measured 5-10% faster there than row by row.
   Out *Wg = reinterpret_cast<Out *>(w.W) + (long)g * vp2 * vp;
   const int nT = vp >> 3;
+  auto put = [&](int rb_, int cb, int r, long m, int p0, int p1) __attribute__((always_inline)) {
+    const int n = n0 + cb * 16 + fr;
+    if (m < M && n < vp) {
+      int a, b, c;
+      if (g == 0) { a = p0; b = p1; c = n; }
+      else if (g == 1) { a = n; b = p0; c = p1; }
+      else { a = p0; b = n; c = p1; }
+      Out x = (Out)acc[rb_][cb][r];
+      if constexpr (TR::SCALED) x *= w.scale;
+      gst(Wg + box_off(a, b, c, nT), x);
+    }
+  };
 #pragma unroll
-  for (int rb_ = 0; rb_ < WM; ++rb_)
+  for (int rb_ = 0; rb_ < WM; ++rb_) {
+    long m[4];
+    int p0[4], p1[4];
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb)
+    for (int r = 0; r < 4; ++r) {
+      m[r] = m0 + wrow + rb_ * 16 + (TR::ROWQ == 1 ? fk + 4 * r : fk * 4 + r);
+      p0[r] = (int)(m[r] / vp);
+      p1[r] = (int)(m[r] - (long)p0[r] * vp);
+    }
+    if constexpr (TR::ROWQ == 1) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        long m = m0 + wrow + rb_ * 16 + (TR::ROWQ == 1 ? fk + 4 * r : fk * 4 + r);
-        int n = n0 + cb * 16 + fr;
-        if (m < M && n < vp) {
-          int p0 = (int)(m / vp), p1 = (int)(m - (long)p0 * vp);
-          int a, b, c;
-          if (g == 0) { a = p0; b = p1; c = n; }
-          else if (g == 1) { a = n; b = p0; c = p1; }
-          else { a = p0; b = n; c = p1; }
-          Out x = (Out)acc[rb_][cb][r];
-          if constexpr (TR::SCALED) x *= w.scale;
-          gst(Wg + box_off(a, b, c, nT), x);
-        }
-      }
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) put(rb_, cb, r, m[r], p0[r], p1[r]);
+    } else {
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) put(rb_, cb, r, m[r], p0[r], p1[r]);
+    }
+  }
 }
 
 }  // namespace
@@ -482,7 +500,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void wb
 // ------------------------------------------------------------ launchers
 // Tile shape: two 16-row blocks per wave in every precision, and the
 // column-block count NB in [4, 8] that minimises padded waste of the lone
-// index (larger NB on ties).
+// index (larger NB on ties). (Wide tiles at one workgroup per CU, 256 x 208
+// or 128 x 400, load half the operand bytes per MFMA but ran the 16-bit and
+// FP32 W builds 3-19% slower than three 128 x 80 workgroups per CU.)
 WConfig wbuild_config(Prec, int vp) {
   WConfig c;
   c.wm = 2;
