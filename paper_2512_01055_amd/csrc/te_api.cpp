@@ -502,8 +502,10 @@ double flops_per_triple(int o, int v) { return 12.0 * (double)v * v * v * ((doub
 
 // Triples per launch: at least 64k workgroup tiles (about 85 waves of
 // workgroups over the chip), so that the last, partly filled wave of a
-// launch costs little; W scratch for two batches in flight within 16 GB or
-// an eighth of the budget.
+// launch costs little. The W scratch of one batch stays within 2 GB or four
+// triples' worth, whichever is larger, and within a sixteenth of the budget:
+// a small job's call then allocates (and frees) a few GB, not the 16 GB that
+// 64k of its small tiles would take.
 static int batch_size(const Job &J, Prec p, long ntr) {
   const WConfig wc = wbuild_config(p, J.vp);
   const long mt = ((long)J.vp * J.vp + wc.bm() - 1) / wc.bm();
@@ -511,7 +513,8 @@ static int batch_size(const Job &J, Prec p, long ntr) {
   const long tiles = 3 * mt * nt;
   long b = std::max(1L, (65536 + tiles - 1) / tiles);
   const size_t per = 3 * (size_t)J.vp * J.vp * J.vp * out_size(p);
-  const size_t cap = std::max<size_t>(per, std::min<size_t>((size_t)16 << 30, J.budget / 8) / 2);
+  const size_t cap = std::max<size_t>(
+      per, std::min<size_t>(std::max<size_t>(4 * per, (size_t)2 << 30), J.budget / 16));
   b = std::min<long>(b, std::max<long>(1, (long)(cap / per)));
   b = std::min<long>(b, ntr);
   return (int)std::max(1L, b);
