@@ -502,10 +502,11 @@ double flops_per_triple(int o, int v) { return 12.0 * (double)v * v * v * ((doub
 
 // Triples per launch: at least 64k workgroup tiles (about 85 waves of
 // workgroups over the chip), so that the last, partly filled wave of a
-// launch costs little. The W scratch of one batch stays within 2 GB or four
-// triples' worth, whichever is larger, and within a sixteenth of the budget:
-// a small job's call then allocates (and frees) a few GB, not the 16 GB that
-// 64k of its small tiles would take.
+// launch costs little. The W scratch of one batch stays within 8 GB, a
+// sixteenth of the budget, and a 64th of the W of all the call's triples
+// (but may take 256 MB): allocating (and freeing) scratch costs about 12 ms
+// per GB, which a small job's whole evaluation would not cover (o=16, v=128
+// took three times as long with 16 GB of scratch).
 static int batch_size(const Job &J, Prec p, long ntr) {
   const WConfig wc = wbuild_config(p, J.vp);
   const long mt = ((long)J.vp * J.vp + wc.bm() - 1) / wc.bm();
@@ -514,7 +515,8 @@ static int batch_size(const Job &J, Prec p, long ntr) {
   long b = std::max(1L, (65536 + tiles - 1) / tiles);
   const size_t per = 3 * (size_t)J.vp * J.vp * J.vp * out_size(p);
   const size_t cap = std::max<size_t>(
-      per, std::min<size_t>(std::max<size_t>(4 * per, (size_t)2 << 30), J.budget / 16));
+      per, std::min({(size_t)8 << 30, J.budget / 16,
+                     std::max<size_t>((size_t)ntr * per / 64, (size_t)256 << 20)}));
   b = std::min<long>(b, std::max<long>(1, (long)(cap / per)));
   b = std::min<long>(b, ntr);
   return (int)std::max(1L, b);
@@ -716,11 +718,18 @@ void resident_items(const Job &J, const Operands &op, Prec p, int i, int j, int 
 
 // (px|qy) for one occupied pair as a v x v block with row stride vp (Eq. 6
 // with two (ov) factors), on stream s.
-static void assemble_k_block(Job &J, int p, int q, double *dst, hipStream_t s) {
+// The three (ov|ov) blocks of triple (i, j, k) the singles term reads,
+// (jb|kc), (ia|kc), (ia|jb) = sum_Q B^Q B^Q (Eq. 6), into dst[0..2] (v x vp
+// each), in one launch.
+static void assemble_k_blocks(Job &J, int i, int j, int k, double *dst, hipStream_t s) {
   const int o = J.o, v = J.v, vp = J.vp;
-  GemmTN g{J.Bov + (long)p * v, J.Bov + (long)q * v, dst, v, v, J.naux, (long)o * v,
-           (long)o * v, v, 0, vp, v, 0, 1, 1.0};
-  HIPCHK(launch_gemm_tn(g, s));
+  const size_t kblk = (size_t)vp * vp;
+  const int pq[3][2] = {{j, k}, {i, k}, {i, j}};
+  GemmTN g[3];
+  for (int z = 0; z < 3; ++z)
+    g[z] = GemmTN{J.Bov + (long)pq[z][0] * v, J.Bov + (long)pq[z][1] * v, dst + z * kblk, v, v,
+                  J.naux, (long)o * v, (long)o * v, v, 0, vp, v, 0, 1, 1.0};
+  HIPCHK(launch_gemm_tn_batch(g, 3, s));
 }
 
 void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double *per_triple,
@@ -932,9 +941,7 @@ void run_triples(Job &J, Prec p, const int *ijk, long ntr, double *e_sum, double
         const long t = P.order[first + q];
         const int i = ijk[3 * t], j = ijk[3 * t + 1], k = ijk[3 * t + 2];
         double *kb = kbuf.as<double>() + ((size_t)slot * B + q) * 3 * kblk;
-        assemble_k_block(J, j, k, kb, J.s_main);
-        assemble_k_block(J, i, k, kb + kblk, J.s_main);
-        assemble_k_block(J, i, j, kb + 2 * kblk, J.s_main);
+        assemble_k_blocks(J, i, j, k, kb, J.s_main);
       }
     }
     HIPCHK(hipStreamWaitEvent(J.s_main, J.ev_w[slot], 0));

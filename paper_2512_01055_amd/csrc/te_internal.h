@@ -101,6 +101,8 @@ hipError_t launch_energy(bool w_is_f64, const EItem *d_items, const int *d_blk_i
 hipError_t launch_reduce(const RItem *d_items, int nitems, hipStream_t s);
 hipError_t launch_sum(const double *x, long n, double *out, hipStream_t s);
 hipError_t launch_gemm_tn(const GemmTN &g, hipStream_t s);
+// up to three independent products in one launch (one grid layer each)
+hipError_t launch_gemm_tn_batch(const GemmTN *g, int n, hipStream_t s);
 hipError_t launch_pad4(const double *src, double *dst, int d0, int d1, int d2, int d3,
                        int p1, int p2, int p3, double scale, hipStream_t s);
 hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t s);

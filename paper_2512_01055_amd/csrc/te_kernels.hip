@@ -311,11 +311,18 @@ __global__ __launch_bounds__(1024) void sum_kernel(const double *__restrict__ x,
 // ------------------------------------------------------------ staging GEMM
 constexpr int GT = 64, GK = 16;
 
-__global__ __launch_bounds__(WG) void gemm_tn_kernel(GemmTN g) {
+// Independent products of one launch; grid layer z computes g[z].
+struct GemmTNBatch {
+  GemmTN g[3];
+};
+
+__global__ __launch_bounds__(WG) void gemm_tn_kernel(GemmTNBatch gb) {
   __shared__ __attribute__((aligned(16))) double As[GK][GT];
   __shared__ __attribute__((aligned(16))) double Bs[GK][GT];
+  const GemmTN &g = gb.g[blockIdx.z];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+  if (m0 >= g.M || n0 >= g.N) return;   // a layer smaller than the grid
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   d4 acc[2][2];
   for (int a = 0; a < 2; ++a)
@@ -684,12 +691,25 @@ hipError_t launch_sum(const double *x, long n, double *out, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_gemm_tn_batch(const GemmTN *g, int n, hipStream_t s) {
+  if (n < 1 || n > 3) return hipErrorInvalidValue;
+  GemmTNBatch gb{};
+  int mx = 0, nx = 0;
+  for (int z = 0; z < n; ++z) {
+    if (g[z].M <= 0 || g[z].N <= 0) return hipErrorInvalidValue;
+    gb.g[z] = g[z];
+    mx = std::max(mx, (g[z].M + GT - 1) / GT);
+    nx = std::max(nx, (g[z].N + GT - 1) / GT);
+  }
+  dim3 grid(mx, nx, n);
+  if (grid.y > 65535) return hipErrorInvalidValue;
+  gemm_tn_kernel<<<grid, dim3(WG), 0, s>>>(gb);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm_tn(const GemmTN &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  dim3 grid((g.M + GT - 1) / GT, (g.N + GT - 1) / GT);
-  if (grid.y > 65535) return hipErrorInvalidValue;
-  gemm_tn_kernel<<<grid, dim3(WG), 0, s>>>(g);
-  return hipGetLastError();
+  return launch_gemm_tn_batch(&g, 1, s);
 }
 
 static unsigned blocks_for(size_t n) {
